@@ -1,0 +1,168 @@
+/*
+ * symhss: symmetric Muller-like HSS direct solver for 2-D Helmholtz
+ * transmission scattering, on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper Section 2): find u (boundary trace of the field) and
+ * q = (1/eps) du/dnu on a closed C^2 curve Gamma between an exterior medium
+ * (k0, eps0) and an interior one (k1, eps1), for an incident wave u_in.
+ * The discretisation (Section 3.1) is the N-point trapezoidal Nystrom rule
+ * in the 2 pi-periodic parameter with one-point corrected diagonals; the
+ * system (Section 3.2, eq. symmetric_muller) has 2N unknowns [q; u] and is
+ * complex symmetric up to its free terms.  The solver (Section 4) compresses
+ * every off-diagonal block with the proxy method and an interpolative
+ * decomposition; with symmetry one ID per half-box serves as left and right
+ * basis (eq. low-rank_R).
+ *
+ * Calling order: create -> assemble -> compress -> factor -> solve (any
+ * number of times).  assemble invalidates later stages; calls out of order
+ * return SYMHSS_ESTATE.  Every call returns a status and never aborts; the
+ * message of the last failure is symhss_last_error().  A context is not
+ * thread-safe: use one per host thread.  The context owns every device
+ * allocation; the caller owns all arrays it passes, which are only read or
+ * written during the call.
+ */
+#ifndef SYMHSS_H
+#define SYMHSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct symhss_ctx symhss_ctx;
+
+/* complex FP64, layout-compatible with C99 double _Complex and torch.complex128 */
+typedef struct {
+  double re, im;
+} symhss_z;
+
+typedef enum {
+  SYMHSS_OK = 0,
+  SYMHSS_EINVAL = 1,    /* bad argument: sizes, non-finite geometry, zero speed, k <= 0 */
+  SYMHSS_ENOMEM = 2,    /* device or host allocation failed */
+  SYMHSS_EDEVICE = 3,   /* HIP runtime error */
+  SYMHSS_ESTATE = 4,    /* call out of order */
+  SYMHSS_ESINGULAR = 5, /* zero pivot in a diagonal-block LU */
+  SYMHSS_ERANK = 6      /* proxy matrix beyond the ID kernel's limits */
+} symhss_status;
+
+typedef enum {
+  /* eq. symmetric_muller, one-sided ID: L_i = R_i^T (the paper's method) */
+  SYMHSS_MULLER_SYM = 0,
+  /* eq. naive_muller (unscaled), two-sided ID of M_R and M_L (the paper's Base) */
+  SYMHSS_MULLER_BASE = 1,
+  /* ablation: the symmetric matrix compressed two-sided, symmetry unused */
+  SYMHSS_MULLER_SYM_TWOSIDED = 2
+} symhss_form;
+
+/* Materials: k_i = omega sqrt(eps_i) > 0 (Section 2); eps_i > 0. */
+typedef struct {
+  double k0, k1, eps0, eps1;
+} symhss_medium;
+
+typedef struct {
+  int32_t leaf;        /* points per leaf box (>= 8); tree levels L = ceil(log2(N/leaf)) */
+  int32_t form;        /* symhss_form */
+  double tol;          /* relative ID tolerance: rank = #{j : |R_jj| > tol |R_00|}, > 0 */
+  int32_t n_proxy;     /* minimum proxy points per circle (e.g. 64) */
+  int32_t pad0;
+  double proxy_ratio;  /* proxy radius / box radius (e.g. 1.5) */
+} symhss_opts;
+
+/* Flag for solve/rhs/matvec: arrays are device pointers (HBM) rather than host. */
+#define SYMHSS_DEVICE_PTRS 1
+
+/* Create a context on HIP device `device`; `hip_stream` (a hipStream_t) may
+ * be NULL, in which case the context creates its own stream. */
+symhss_status symhss_create(symhss_ctx **out, int device, void *hip_stream);
+void symhss_destroy(symhss_ctx *ctx);
+/* Message of the last failed call on ctx; with ctx == NULL, of the last failed
+ * symhss_create on this thread. */
+const char *symhss_last_error(const symhss_ctx *ctx);
+/* The stream all work is queued on (a hipStream_t). */
+void *symhss_stream(symhss_ctx *ctx);
+
+/* Discretisation (Section 3.1).  theta_j = 2 pi j / N, j = 0..N-1, counter-
+ * clockwise.  x, dx, ddx: host arrays of N x 2 interleaved doubles holding
+ * x(theta_j), x'(theta_j), x''(theta_j); copied to the device.  Computes the
+ * normals (into the exterior), curvature and weights w_j = |x'_j| 2 pi / N on
+ * the GPU and builds the box tree.  EINVAL for N < 2 leaf, non-finite values,
+ * |x'| = 0, k or eps <= 0, tol <= 0. */
+symhss_status symhss_assemble(symhss_ctx *ctx, int64_t n, const double *x, const double *dx, const double *ddx,
+                              const symhss_medium *medium, const symhss_opts *opts);
+
+/* Proxy-method compression (Section 4.1), levels L..1: generates M_R (and
+ * M_L for the two-sided forms) on the GPU and computes the column-pivoted
+ * QR IDs of their halves. */
+symhss_status symhss_compress(symhss_ctx *ctx);
+
+/* Compressed-equation factorisation (Section 4.2): per box LU of the
+ * diagonal block D, X = D^{-1} L, A~ = (R X)^{-1}; parent blocks
+ * [[A~_c1, S_c1c2], [S_c2c1, A~_c2]]; dense LU at the root.  ESINGULAR on a
+ * zero pivot. */
+symhss_status symhss_factor(symhss_ctx *ctx);
+
+/* Solve A x = b for nrhs right-hand sides.  b and x are 2N x nrhs column-
+ * major in the block order [q; u] and the scaling of the chosen form (row-
+ * scaled for SYMHSS_MULLER_SYM*, unscaled for SYMHSS_MULLER_BASE).  Host
+ * pointers unless flags has SYMHSS_DEVICE_PTRS.  b and x may not overlap. */
+symhss_status symhss_solve(symhss_ctx *ctx, const symhss_z *b, symhss_z *x, int32_t nrhs, int32_t flags);
+
+/* Right-hand side of the chosen form for the plane wave
+ * u_in = exp(i k0 (cos a x1 + sin a x2)), q_in = du_in/dnu:
+ * b = [-eps0 W u_in; W q_in] (eq. symmetric_muller) or [-eps0 u_in; q_in]. */
+symhss_status symhss_rhs_plane_wave(symhss_ctx *ctx, double angle, symhss_z *b, int32_t flags);
+
+/* Verification: entries A[rows][:, cols] of the 2N x 2N system (indices
+ * < N: first equation / q unknown of node i; N + i: second equation / u
+ * unknown), out is nr x nc column-major, host memory.  Valid after assemble. */
+symhss_status symhss_eval_entries(symhss_ctx *ctx, int64_t nr, const int64_t *rows, int64_t nc,
+                                  const int64_t *cols, symhss_z *out);
+
+/* Verification: J0, Y0, J1, Y1, Y1 + 2/(pi z) at n points z > 0 (out: 5n
+ * doubles), evaluated by the device code used for the kernel entries. */
+symhss_status symhss_eval_bessel(symhss_ctx *ctx, int64_t n, const double *z, double *out);
+
+/* y = A x with every entry generated on the fly in FP64 (no storage; O(N^2)
+ * work).  x, y: 2N complex; host pointers unless SYMHSS_DEVICE_PTRS. */
+symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z *y, int32_t flags);
+
+/* Statistics of the last assemble/compress/factor/solve. */
+typedef struct {
+  int32_t levels;            /* L */
+  int32_t leaf_boxes;        /* 2^L */
+  int32_t root_size;         /* order of the root system */
+  int32_t form;
+  int64_t entries_compress;  /* matrix entries generated by compress */
+  int64_t entries_factor;    /* matrix entries generated by factor */
+  double t_compress, t_factor, t_solve;          /* seconds, host wall clock incl. sync */
+  double t_kblock_compress, t_kblock_factor;     /* seconds in the kernel-block generator (HIP events) */
+  double t_id, t_lu;                             /* seconds in ID and LU kernels (HIP events) */
+  int64_t device_bytes;
+  int32_t rank_min[32], rank_max[32]; /* per level (index = level), q + u rank of a box */
+  double rank_mean[32];
+  int32_t proxy_max[32];     /* largest proxy count per level */
+} symhss_stats;
+
+symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);
+
+/* Verification: data of one box after compress.  `what` selects:
+ *  0/1  active column node ids (q / u half)      2/3  active row node ids (eq 1 / eq 2)
+ *  4/5  column skeleton, local indices (q / u)    6/7  row skeleton, local indices
+ *  8    dense column interpolation R (kc x sc, complex, column-major)
+ *  9    dense row interpolation L (sr x kr)
+ *  10   proxy circle: centre x, centre y, radius, count (4 doubles)
+ *  11/12 near row node ids (eq 1 / eq 2)          13/14 near column node ids (q / u)
+ *  15   ranks kc_q, kc_u, kr_q, kr_u (4 int32)
+ * Element type: int32 for ids/indices/ranks, symhss_z for 8/9, double for 10.
+ * With out == NULL only *count is set; otherwise out must hold *count elements. */
+symhss_status symhss_box_query(symhss_ctx *ctx, int32_t level, int32_t box, int32_t what, int64_t *count,
+                               void *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYMHSS_H */

@@ -1,0 +1,245 @@
+"""Python binding of the symhss C-ABI (include/symhss.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module converts
+NumPy / torch arrays to pointers and status codes to exceptions.  If the
+library is missing it raises: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsymhss.so")
+
+MULLER_SYM, MULLER_BASE, MULLER_SYM_TWOSIDED = 0, 1, 2
+DEVICE_PTRS = 1
+
+_STATUS = {
+    0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ESINGULAR", 6: "ERANK",
+}
+
+
+class SymhssError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"symhss {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Medium(ctypes.Structure):
+    _fields_ = [("k0", ctypes.c_double), ("k1", ctypes.c_double),
+                ("eps0", ctypes.c_double), ("eps1", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("form", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("n_proxy", ctypes.c_int32), ("pad0", ctypes.c_int32), ("proxy_ratio", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("leaf_boxes", ctypes.c_int32), ("root_size", ctypes.c_int32),
+                ("form", ctypes.c_int32),
+                ("entries_compress", ctypes.c_int64), ("entries_factor", ctypes.c_int64),
+                ("t_compress", ctypes.c_double), ("t_factor", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("t_kblock_compress", ctypes.c_double), ("t_kblock_factor", ctypes.c_double),
+                ("t_id", ctypes.c_double), ("t_lu", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64),
+                ("rank_min", ctypes.c_int32 * 32), ("rank_max", ctypes.c_int32 * 32),
+                ("rank_mean", ctypes.c_double * 32), ("proxy_max", ctypes.c_int32 * 32)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("rank") and f != "proxy_max"}
+        L = self.levels
+        d["rank_min"] = list(self.rank_min[1:L + 1])
+        d["rank_max"] = list(self.rank_max[1:L + 1])
+        d["rank_mean"] = [round(v, 2) for v in self.rank_mean[1:L + 1]]
+        d["proxy_max"] = list(self.proxy_max[1:L + 1])
+        return d
+
+
+EXPORTS = [
+    "symhss_create", "symhss_destroy", "symhss_last_error", "symhss_stream", "symhss_assemble",
+    "symhss_compress", "symhss_factor", "symhss_solve", "symhss_rhs_plane_wave", "symhss_eval_entries",
+    "symhss_eval_bessel", "symhss_matvec_direct", "symhss_get_stats", "symhss_box_query",
+]
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libsymhss.so (built in-tree by paper_2609_33216_amd.build)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    try:
+        # The library links libamdhip64.so.7 by soname; when torch is present its
+        # bundled HIP runtime must be the one loaded, so that one runtime serves
+        # both (torch tensors' device memory and streams are then usable here).
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2609_33216_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "symhss_create": ([ctypes.POINTER(vp), ctypes.c_int, vp], ctypes.c_int),
+        "symhss_destroy": ([vp], None),
+        "symhss_last_error": ([vp], ctypes.c_char_p),
+        "symhss_stream": ([vp], vp),
+        "symhss_assemble": ([vp, i64, vp, vp, vp, ctypes.POINTER(Medium), ctypes.POINTER(Opts)], ctypes.c_int),
+        "symhss_compress": ([vp], ctypes.c_int),
+        "symhss_factor": ([vp], ctypes.c_int),
+        "symhss_solve": ([vp, vp, vp, i32, i32], ctypes.c_int),
+        "symhss_rhs_plane_wave": ([vp, dbl, vp, i32], ctypes.c_int),
+        "symhss_eval_entries": ([vp, i64, vp, i64, vp, vp], ctypes.c_int),
+        "symhss_eval_bessel": ([vp, i64, vp, vp], ctypes.c_int),
+        "symhss_matvec_direct": ([vp, vp, vp, i32], ctypes.c_int),
+        "symhss_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
+        "symhss_box_query": ([vp, i32, i32, i32, ctypes.POINTER(i64), vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Solver:
+    """One solver context on one GPU."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load()
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    torch.cuda.set_device(device)
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except ImportError:
+                stream = None
+        h = ctypes.c_void_p()
+        st = self.lib.symhss_create(ctypes.byref(h), device, ctypes.c_void_p(stream) if stream else None)
+        if st != 0:
+            raise SymhssError(st, "cannot create a context: " + self.lib.symhss_last_error(None).decode())
+        self.h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.symhss_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != 0:
+            raise SymhssError(st, self.lib.symhss_last_error(self.h).decode())
+
+    # -- main verbs ------------------------------------------------------
+    def assemble(self, x, dx, ddx, k0: float, k1: float, eps0: float = 1.0, eps1: float | None = None,
+                 leaf: int = 128, tol: float = 1e-10, form: int = MULLER_SYM, n_proxy: int = 64,
+                 proxy_ratio: float = 1.5):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        dx = np.ascontiguousarray(dx, dtype=np.float64)
+        ddx = np.ascontiguousarray(ddx, dtype=np.float64)
+        if x.ndim != 2 or x.shape[1] != 2 or dx.shape != x.shape or ddx.shape != x.shape:
+            raise ValueError("x, dx, ddx must be (N, 2) arrays")
+        if eps1 is None:
+            eps1 = (k1 / k0) ** 2 * eps0
+        med = Medium(k0, k1, eps0, eps1)
+        opt = Opts(leaf, form, tol, n_proxy, 0, proxy_ratio)
+        self._check(self.lib.symhss_assemble(self.h, x.shape[0], _ptr(x), _ptr(dx), _ptr(ddx),
+                                             ctypes.byref(med), ctypes.byref(opt)))
+        self.n = x.shape[0]
+
+    def compress(self):
+        self._check(self.lib.symhss_compress(self.h))
+
+    def factor(self):
+        self._check(self.lib.symhss_factor(self.h))
+
+    def solve(self, b):
+        """b: (2N,) or (2N, nrhs) complex; returns x of the same shape (host arrays)."""
+        b = np.asarray(b, dtype=np.complex128)
+        one = b.ndim == 1
+        B = np.asfortranarray(b.reshape(b.shape[0], -1))
+        if B.shape[0] != 2 * self.n:
+            raise ValueError("b must have 2N rows")
+        X = np.zeros_like(B, order="F")
+        self._check(self.lib.symhss_solve(self.h, _ptr(B), _ptr(X), B.shape[1], 0))
+        return X[:, 0].copy() if one else X
+
+    def solve_device(self, b_ptr: int, x_ptr: int, nrhs: int = 1):
+        """Device-resident solve: b_ptr, x_ptr are HBM addresses of 2N x nrhs complex128."""
+        self._check(self.lib.symhss_solve(self.h, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), nrhs,
+                                          DEVICE_PTRS))
+
+    def rhs_plane_wave(self, angle: float):
+        b = np.zeros(2 * self.n, dtype=np.complex128)
+        self._check(self.lib.symhss_rhs_plane_wave(self.h, angle, _ptr(b), 0))
+        return b
+
+    def rhs_plane_wave_device(self, angle: float, b_ptr: int):
+        self._check(self.lib.symhss_rhs_plane_wave(self.h, angle, ctypes.c_void_p(b_ptr), DEVICE_PTRS))
+
+    def eval_entries(self, rows, cols):
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        out = np.zeros((len(rows), len(cols)), dtype=np.complex128, order="F")
+        self._check(self.lib.symhss_eval_entries(self.h, len(rows), _ptr(rows), len(cols), _ptr(cols), _ptr(out)))
+        return out
+
+    def eval_bessel(self, z):
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        out = np.zeros((len(z), 5), dtype=np.float64)
+        self._check(self.lib.symhss_eval_bessel(self.h, len(z), _ptr(z), _ptr(out)))
+        return out
+
+    def matvec_direct(self, x):
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.zeros_like(x)
+        self._check(self.lib.symhss_matvec_direct(self.h, _ptr(x), _ptr(y), 0))
+        return y
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.symhss_get_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def box_query(self, level: int, box: int, what: int):
+        cnt = ctypes.c_int64(0)
+        self._check(self.lib.symhss_box_query(self.h, level, box, what, ctypes.byref(cnt), None))
+        n = cnt.value
+        if what in (8, 9):
+            out = np.zeros(n, dtype=np.complex128)
+        elif what == 10:
+            out = np.zeros(n, dtype=np.float64)
+        else:
+            out = np.zeros(n, dtype=np.int32)
+        if n:
+            self._check(self.lib.symhss_box_query(self.h, level, box, what, ctypes.byref(cnt), _ptr(out)))
+        return out
+
+    def box_interp(self, level: int, box: int):
+        """(R, L) dense interpolation matrices of a box (column-major from the device)."""
+        kcq, kcu, krq, kru = self.box_query(level, box, 15)
+        sc = len(self.box_query(level, box, 0)) + len(self.box_query(level, box, 1))
+        sr = len(self.box_query(level, box, 2)) + len(self.box_query(level, box, 3))
+        R = self.box_query(level, box, 8).reshape(sc, kcq + kcu).T
+        L = self.box_query(level, box, 9).reshape(krq + kru, sr).T
+        return R, L

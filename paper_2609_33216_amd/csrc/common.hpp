@@ -1,0 +1,101 @@
+// Shared types of the HIP path: complex FP64 arithmetic, device descriptors
+// and launch helpers.  Host and device code both include this header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+namespace symhss {
+
+struct cplx {
+  double re, im;
+};
+
+__host__ __device__ inline cplx mk(double r, double i) { return cplx{r, i}; }
+__host__ __device__ inline cplx operator+(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cplx operator-(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cplx operator-(cplx a) { return {-a.re, -a.im}; }
+__host__ __device__ inline cplx operator*(cplx a, cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cplx operator*(double s, cplx a) { return {s * a.re, s * a.im}; }
+__host__ __device__ inline cplx conj(cplx a) { return {a.re, -a.im}; }
+__host__ __device__ inline double abs2(cplx a) { return a.re * a.re + a.im * a.im; }
+// a += b * c
+__host__ __device__ inline void fma_acc(cplx& a, cplx b, cplx c) {
+  a.re = fma(b.re, c.re, fma(-b.im, c.im, a.re));
+  a.im = fma(b.re, c.im, fma(b.im, c.re, a.im));
+}
+// a += conj(b) * c
+__host__ __device__ inline void fma_conj_acc(cplx& a, cplx b, cplx c) {
+  a.re = fma(b.re, c.re, fma(b.im, c.im, a.re));
+  a.im = fma(b.re, c.im, fma(-b.im, c.re, a.im));
+}
+__host__ __device__ inline cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double r = b.im / b.re, d = b.re + b.im * r;
+    return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  }
+  const double r = b.re / b.im, d = b.im + b.re * r;
+  return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+
+// Boundary and proxy points, structure of arrays.  Index < n_boundary is a
+// boundary node; larger indices are proxy points of the current level.
+struct PointsDev {
+  const double* x;
+  const double* y;
+  const double* nx;
+  const double* ny;
+  const double* w;
+  const double* kappa;  // curvature (boundary nodes only)
+  int n_boundary;
+};
+
+// Medium constants.  eps0, eps1 and the wavenumbers; the remaining fields are
+// the point-independent parts of the one-point corrected diagonals.
+struct MediumDev {
+  double k0, k1, eps0, eps1;
+  double g0c, g1c;      // ln(k/2) + gamma for k0, k1
+  double nd_re, nd_im;  // N_k0 - N_k1 diagonal without the -(Delta/4pi) ln(w/2pi) term
+  double delta;         // k0^2 - k1^2
+  int row_scaled;       // 1: eq. symmetric_muller; 0: eq. naive_muller
+};
+
+// One block job of the kernel-block generator: the 2x2 Muller-like block
+// between row points and column points, written into a column-major matrix.
+// For row point a: rmap1[a] / rmap2[a] is the output row of its first /
+// second equation (-1: not wanted).  For column point b: cmap1[b] / cmap2[b]
+// is the output column of its q / u unknown.  mode 0 writes out[rmap, cmap];
+// mode 1 also writes the transposed position out[cmap, rmap] (valid when row
+// and column positions share one index space and the matrix is symmetric);
+// mode 2 writes only out[cmap, rmap] (a block stored transposed, e.g. M_L^T).
+struct KJob {
+  cplx* out;
+  int ld;
+  int nr, nc;
+  int roff, coff;  // offsets into the row / column index arrays
+  int mode;
+  int pad;
+};
+
+struct KTile {
+  int job, r0, c0, pad;
+};
+
+inline void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+#define HIPCHK(x) ::symhss::hip_check((x), #x)
+
+inline int cdiv_int(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace symhss

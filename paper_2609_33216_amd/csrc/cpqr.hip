@@ -1,0 +1,258 @@
+// Interpolative decomposition of proxy matrices by column-pivoted
+// Householder QR (paper Section 4.1: the ID of each half of M_R, and for the
+// two-sided baseline of each half of M_L^T).
+//
+// For M (m x n, column-major, in place): M P = Q R.  Pivot j is the remaining
+// column of largest trailing norm (lowest index on ties); trailing norms are
+// recomputed exactly while each column is updated, so no downdating error
+// accumulates.  The rank k is the first j with |R_jj| <= tol |R_00|
+// (tolerance mode) or a fixed target (resume mode, used to equalise row and
+// column ranks in the two-sided baseline).  Afterwards (want_T) T = R11^{-1}
+// R12 overwrites R12, so that M[:, P[k:]] ~= M[:, P[:k]] T; a pass that may
+// be resumed leaves R12 in place.
+//
+// One workgroup (4 wavefronts) per matrix.  The Householder vector of the
+// current step is staged in LDS; every wavefront then takes a stride of the
+// trailing columns, forms v^H a_c with a wavefront reduction, applies the
+// reflector and recomputes the column's trailing norm in the same pass.
+#include "kernels.hpp"
+
+namespace symhss {
+
+
+constexpr int kIdThreads = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ descs, double tol, int want_T) {
+  extern __shared__ double lds[];
+  const IdDesc D = descs[blockIdx.x];
+  const int m = D.m, n = D.n;
+  const long ld = D.ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int nwaves = kIdThreads / 64;
+  // LDS: vn[n] doubles, v[m] complex, reduction scratch
+  double* vn = lds;
+  cplx* v = reinterpret_cast<cplx*>(lds + n);
+  double* red = lds + n + 2 * m;           // nwaves doubles
+  int* redi = reinterpret_cast<int*>(red + nwaves);  // nwaves ints
+  __shared__ int s_piv;
+  __shared__ int s_stop;
+  __shared__ double s_tau;
+
+  const int kmax = m < n ? m : n;
+  int j0 = (D.target >= 0) ? *D.rank : 0;
+  if (j0 == 0) {
+    for (int c = tid; c < n; c += kIdThreads) D.perm[c] = c;
+  }
+  __syncthreads();
+  // trailing norms over rows j0..m-1
+  for (int c = wave; c < n; c += nwaves) {
+    double s = 0.0;
+    if (c >= j0) {
+      const cplx* col = D.A + ld * c;
+      for (int i = j0 + lane; i < m; i += 64) s += abs2(col[i]);
+    }
+    s = wave_sum(s);
+    if (lane == 0) vn[c] = s;
+  }
+  __syncthreads();
+  double r00 = (j0 > 0) ? *D.r00 : 0.0;
+  int j = j0;
+  for (; j < kmax; ++j) {
+    // pivot: argmax vn[c], c >= j, lowest index on ties
+    double best = -1.0;
+    int bi = n;
+    for (int c = j + tid; c < n; c += kIdThreads) {
+      const double x = vn[c];
+      if (x > best) { best = x; bi = c; }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { red[wave] = best; redi[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = red[0];
+      int ix = redi[0];
+      for (int w = 1; w < nwaves; ++w) {
+        if (red[w] > b || (red[w] == b && redi[w] < ix)) { b = red[w]; ix = redi[w]; }
+      }
+      const double nrm = sqrt(b > 0.0 ? b : 0.0);
+      int stop = 0;
+      if (j == 0) r00 = nrm;
+      if (D.target >= 0) {
+        stop = (j >= D.target);
+      } else {
+        stop = !(r00 > 0.0) || !(nrm > tol * r00);  // NaN-safe
+      }
+      if (ix >= n) stop = 1;  // no admissible pivot (non-finite norms)
+      if (j == 0) *D.r00 = r00;
+      s_stop = stop;
+      s_piv = ix;
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int p = s_piv;
+    if (p != j) {
+      cplx* cj = D.A + ld * j;
+      cplx* cp = D.A + ld * p;
+      for (int i = tid; i < m; i += kIdThreads) {
+        const cplx t = cj[i];
+        cj[i] = cp[i];
+        cp[i] = t;
+      }
+      if (tid == 0) {
+        const int t = D.perm[j];
+        D.perm[j] = D.perm[p];
+        D.perm[p] = t;
+        const double tv = vn[j];
+        vn[j] = vn[p];
+        vn[p] = tv;
+      }
+    }
+    __syncthreads();
+    // Householder reflector H = I - tau v v^H with v_0 = 1 mapping the pivot
+    // column's trailing part y = [alpha; x] to beta e_1, beta = -e^{i arg alpha} |y|.
+    cplx* cj = D.A + ld * j;
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) s += abs2(cj[i]);
+      s = wave_sum(s);
+      const cplx alpha = cj[j];
+      const double aa = sqrt(abs2(alpha));
+      const double nrm = sqrt(aa * aa + s);
+      cplx beta, u0;
+      double tau;
+      if (nrm == 0.0) {
+        beta = mk(0, 0);
+        u0 = mk(1, 0);
+        tau = 0.0;
+      } else {
+        const cplx ph = aa > 0.0 ? mk(alpha.re / aa, alpha.im / aa) : mk(1, 0);
+        beta = mk(-ph.re * nrm, -ph.im * nrm);
+        u0 = alpha - beta;
+        const double u0a = abs2(u0);
+        tau = 2.0 / (1.0 + s / u0a);
+      }
+      for (int i = j + 1 + lane; i < m; i += 64) {
+        const cplx vi = cdiv(cj[i], u0);
+        v[i] = vi;
+        cj[i] = vi;
+      }
+      if (lane == 0) {
+        v[j] = mk(1, 0);
+        cj[j] = beta;
+        s_tau = tau;
+      }
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    // apply to trailing columns, recompute their norms below row j
+    for (int c = j + 1 + wave; c < n; c += nwaves) {
+      cplx* col = D.A + ld * c;
+      cplx w = mk(0, 0);
+      for (int i = j + lane; i < m; i += 64) fma_conj_acc(w, v[i], col[i]);
+      w.re = wave_sum(w.re);
+      w.im = wave_sum(w.im);
+      const cplx tw = tau * w;
+      double s = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        cplx a = col[i];
+        const cplx vi = v[i];
+        a.re -= vi.re * tw.re - vi.im * tw.im;
+        a.im -= vi.re * tw.im + vi.im * tw.re;
+        col[i] = a;
+        if (i > j) s += abs2(a);
+      }
+      s = wave_sum(s);
+      if (lane == 0) vn[c] = s;
+    }
+    __syncthreads();
+  }
+  const int k = j;
+  if (tid == 0) *D.rank = k;
+  __syncthreads();
+  if (want_T) {
+    // T = R11^{-1} R12 in place, one column per thread
+    for (int c = k + tid; c < n; c += kIdThreads) {
+      cplx* col = D.A + ld * c;
+      for (int i = k - 1; i >= 0; --i) {
+        cplx s = col[i];
+        for (int l = i + 1; l < k; ++l) {
+          const cplx r = D.A[i + ld * l];
+          const cplx x = col[l];
+          s.re -= r.re * x.re - r.im * x.im;
+          s.im -= r.re * x.im + r.im * x.re;
+        }
+        col[i] = cdiv(s, D.A[i + ld * i]);
+      }
+    }
+  }
+}
+
+
+__global__ void k_build_interp(const InterpDesc* __restrict__ descs) {
+  const InterpDesc D = descs[blockIdx.y];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.n) return;
+  const int pc = D.perm[c];
+  const long ldo = D.ldo;
+  if (c < D.k) {
+    const long idx = D.transpose ? (D.col0 + pc) + ldo * (D.row0 + c) : (D.row0 + c) + ldo * (D.col0 + pc);
+    D.out[idx] = mk(1, 0);
+  } else {
+    const cplx* tc = D.A + (long)D.ld * c;
+    for (int r = 0; r < D.k; ++r) {
+      const long idx = D.transpose ? (D.col0 + pc) + ldo * (D.row0 + r) : (D.row0 + r) + ldo * (D.col0 + pc);
+      D.out[idx] = tc[r];
+    }
+  }
+}
+
+// Two-sided baseline: give the two IDs of each (box, half) the same rank
+// max(k_row, k_col), so that the compressed diagonal blocks stay square.
+__global__ void k_equalise_ranks(int npairs, const int* __restrict__ ia, const int* __restrict__ ib,
+                                 IdDesc* descs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  IdDesc& a = descs[ia[i]];
+  IdDesc& b = descs[ib[i]];
+  const int ka = *a.rank, kb = *b.rank;
+  const int k = ka > kb ? ka : kb;
+  a.target = k;
+  b.target = k;
+}
+
+size_t cpqr_lds_bytes(int mmax, int nmax) {
+  return sizeof(double) * (size_t)nmax + sizeof(cplx) * (size_t)mmax + 4 * (sizeof(double) + sizeof(int)) + 64;
+}
+
+void launch_cpqr(hipStream_t st, const IdDesc* descs, int count, int mmax, int nmax, double tol, int want_T) {
+  if (count <= 0) return;
+  const size_t lds = cpqr_lds_bytes(mmax, nmax);
+  if (lds > 160 * 1024) throw std::runtime_error("proxy matrix too large for the ID kernel's LDS staging");
+  hipLaunchKernelGGL(k_cpqr, dim3(count), dim3(kIdThreads), lds, st, descs, tol, want_T);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_build_interp(hipStream_t st, const InterpDesc* descs, int count, int nmax) {
+  if (count <= 0 || nmax <= 0) return;
+  hipLaunchKernelGGL(k_build_interp, dim3(cdiv_int(nmax, 128), count), dim3(128), 0, st, descs);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_equalise_ranks(hipStream_t st, int npairs, const int* ia, const int* ib, IdDesc* descs) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_equalise_ranks, dim3(cdiv_int(npairs, 128)), dim3(128), 0, st, npairs, ia, ib, descs);
+  HIPCHK(hipGetLastError());
+}
+
+}  // namespace symhss

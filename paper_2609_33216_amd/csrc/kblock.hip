@@ -1,0 +1,225 @@
+// Kernel-block generation for the Muller-like 2x2 Nystrom system, FP64.
+//
+// Entry between observation point o and source point s (paper Section 3.1,
+// eq. symmetric_muller / eq. block_A), with d = x_o - x_s, r = |d|,
+// omega = w_o w_s (row-scaled) or w_s (unscaled, eq. naive_muller):
+//   A11 = -omega (i/4) (eps0^2 H0(k0 r) - eps1^2 H0(k1 r))
+//   A12 =  omega (i/4) (eps0 k0 H1(k0 r) - eps1 k1 H1(k1 r)) (d.nu_s)/r
+//   A21 = -omega (i/4) (eps0 k0 H1(k0 r) - eps1 k1 H1(k1 r)) (d.nu_o)/r
+//   A22 = -omega (N_k0 - N_k1),
+//   N_k0 - N_k1 = (i/4) [ dH1 (nu_o.nu_s / r - 2c / r^3) + dH0 c / r^2 ],
+//   c = (d.nu_o)(d.nu_s), dH1 = k0 H1(k0 r) - k1 H1(k1 r), dH0 = k0^2 H0(k0 r) - k1^2 H0(k1 r).
+// k H1(k r) = k J1 + i (k Y1reg(k r) - 2/(pi r)): the 2/(pi r) poles of the
+// two wavenumbers are combined analytically, so dH1 carries no cancellation.
+// On the diagonal (o = s, a boundary node) the one-point corrected values
+// and the free terms -/+ (eps0 + eps1) w / 2 (or 1/2, unscaled) apply.
+//
+// One thread evaluates one point pair and writes its (up to) four entries;
+// the Hankel functions of both wavenumbers are shared by the four.
+#include "kernels.hpp"
+#include "bessel.hpp"
+
+namespace symhss {
+
+__device__ inline void muller_pair(const PointsDev& P, const MediumDev& md, int io, int is,
+                                   cplx e[4]) {
+  const double e0 = md.eps0, e1 = md.eps1;
+  const double wo = P.w[io], ws = P.w[is];
+  const double om = md.row_scaled ? wo * ws : ws;
+  if (io == is && io < P.n_boundary) {
+    const double ell = log(wo * (0.5 / kPi));
+    // G~_k = i/4 - (ln(k/2) + gamma + ell) / (2 pi)
+    const double g0r = -(md.g0c + ell) * (0.5 / kPi);
+    const double g1r = -(md.g1c + ell) * (0.5 / kPi);
+    const double s_re = e0 * e0 * g0r - e1 * e1 * g1r;
+    const double s_im = (e0 * e0 - e1 * e1) * 0.25;
+    e[0] = mk(-om * s_re, -om * s_im);
+    const double dd = (e0 - e1) * (-P.kappa[io] * (0.25 / kPi));
+    const double fr = 0.5 * (e0 + e1) * (md.row_scaled ? wo : 1.0);
+    e[1] = mk(om * dd - fr, 0.0);
+    e[2] = mk(om * dd + fr, 0.0);
+    const double nd_re = md.nd_re - md.delta * (0.25 / kPi) * ell;
+    e[3] = mk(-om * nd_re, -om * md.nd_im);
+    return;
+  }
+  const double dx = P.x[io] - P.x[is];
+  const double dy = P.y[io] - P.y[is];
+  const double r = sqrt(dx * dx + dy * dy);
+  const double invr = 1.0 / r;
+  const double dno = dx * P.nx[io] + dy * P.ny[io];
+  const double dns = dx * P.nx[is] + dy * P.ny[is];
+  const double nn = P.nx[io] * P.nx[is] + P.ny[io] * P.ny[is];
+  const JY01 a = jy01(md.k0 * r);
+  const JY01 b = jy01(md.k1 * r);
+  const double k0 = md.k0, k1 = md.k1;
+  const double pole = kTwoOverPi * invr;  // 2/(pi r)
+  // A11: -(i/4) (eps0^2 H0a - eps1^2 H0b) * om
+  {
+    const double sr = e0 * e0 * a.j0 - e1 * e1 * b.j0;
+    const double si = e0 * e0 * a.y0 - e1 * e1 * b.y0;
+    // (i/4)(sr + i si) = (-si/4, sr/4)
+    e[0] = mk(om * 0.25 * si, -om * 0.25 * sr);
+  }
+  // A12, A21
+  {
+    const double dr_ = e0 * k0 * a.j1 - e1 * k1 * b.j1;
+    const double di_ = e0 * k0 * a.y1r - e1 * k1 * b.y1r - (e0 - e1) * pole;
+    const double ire = -0.25 * di_, iim = 0.25 * dr_;  // (i/4)(dr + i di)
+    const double f12 = om * dns * invr;
+    const double f21 = -om * dno * invr;
+    e[1] = mk(ire * f12, iim * f12);
+    e[2] = mk(ire * f21, iim * f21);
+  }
+  // A22
+  {
+    const double h1r = k0 * a.j1 - k1 * b.j1;
+    const double h1i = k0 * a.y1r - k1 * b.y1r;
+    const double h0r = k0 * k0 * a.j0 - k1 * k1 * b.j0;
+    const double h0i = k0 * k0 * a.y0 - k1 * k1 * b.y0;
+    const double c = dno * dns;
+    const double invr2 = invr * invr;
+    const double f1 = nn * invr - 2.0 * c * invr2 * invr;
+    const double f0 = c * invr2;
+    const double sr = h1r * f1 + h0r * f0;
+    const double si = h1i * f1 + h0i * f0;
+    // -(om) (i/4)(sr + i si) = -om (-si/4, sr/4)
+    e[3] = mk(om * 0.25 * si, -om * 0.25 * sr);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_kblock(PointsDev P, MediumDev md, const KJob* __restrict__ jobs,
+                                                const KTile* __restrict__ tiles,
+                                                const int* __restrict__ rpt, const int* __restrict__ rmap1,
+                                                const int* __restrict__ rmap2, const int* __restrict__ cpt,
+                                                const int* __restrict__ cmap1, const int* __restrict__ cmap2) {
+  const KTile t = tiles[blockIdx.x];
+  const KJob J = jobs[t.job];
+  const int a = t.r0 + (threadIdx.x & 63);
+  const int slot = threadIdx.x >> 6;
+  if (a >= J.nr) return;
+  const int ra = rpt[J.roff + a];
+  const int o1 = rmap1[J.roff + a];
+  const int o2 = rmap2[J.roff + a];
+  const long ld = J.ld;
+  for (int cc = slot; cc < 16; cc += 4) {
+    const int b = t.c0 + cc;
+    if (b >= J.nc) break;
+    const int cb = cpt[J.coff + b];
+    const int c1 = cmap1[J.coff + b];
+    const int c2 = cmap2[J.coff + b];
+    cplx e[4];
+    muller_pair(P, md, ra, cb, e);
+    if (J.mode != 2) {
+      if (o1 >= 0 && c1 >= 0) J.out[o1 + ld * c1] = e[0];
+      if (o1 >= 0 && c2 >= 0) J.out[o1 + ld * c2] = e[1];
+      if (o2 >= 0 && c1 >= 0) J.out[o2 + ld * c1] = e[2];
+      if (o2 >= 0 && c2 >= 0) J.out[o2 + ld * c2] = e[3];
+    }
+    if (J.mode != 0) {
+      // entry (eq e at o, unknown t at s) = entry (eq t at s, unknown e at o)
+      if (o1 >= 0 && c1 >= 0) J.out[c1 + ld * o1] = e[0];
+      if (o1 >= 0 && c2 >= 0) J.out[c2 + ld * o1] = e[1];
+      if (o2 >= 0 && c1 >= 0) J.out[c1 + ld * o2] = e[2];
+      if (o2 >= 0 && c2 >= 0) J.out[c2 + ld * o2] = e[3];
+    }
+  }
+}
+
+// Nystrom geometry (paper Section 3.1): nu = (x2', -x1')/|x'| (into the
+// exterior for a counter-clockwise curve), kappa = (x1' x2'' - x2' x1'')/|x'|^3,
+// w = |x'| 2 pi / N.  Inputs are N x 2 interleaved.
+__global__ void k_geometry(int n, const double* __restrict__ xin, const double* __restrict__ dxin,
+                           const double* __restrict__ ddxin, double* px, double* py, double* nx, double* ny,
+                           double* w, double* kappa) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d0 = dxin[2 * i], d1 = dxin[2 * i + 1];
+  const double s = sqrt(d0 * d0 + d1 * d1);
+  px[i] = xin[2 * i];
+  py[i] = xin[2 * i + 1];
+  nx[i] = d1 / s;
+  ny[i] = -d0 / s;
+  kappa[i] = (d0 * ddxin[2 * i + 1] - d1 * ddxin[2 * i]) / (s * s * s);
+  w[i] = s * (2.0 * kPi / n);
+}
+
+// Plane-wave right-hand side: u_in = exp(i k0 d.x), q_in = i k0 (d.nu) u_in;
+// b = [-eps0 W u_in; W q_in] (row-scaled) or [-eps0 u_in; q_in].
+__global__ void k_rhs_plane(int n, PointsDev P, MediumDev md, double ca, double sa, cplx* b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ph = md.k0 * (ca * P.x[i] + sa * P.y[i]);
+  double s, c;
+  sincos(ph, &s, &c);
+  const double dn = md.k0 * (ca * P.nx[i] + sa * P.ny[i]);
+  const double sc = md.row_scaled ? P.w[i] : 1.0;
+  b[i] = mk(-md.eps0 * sc * c, -md.eps0 * sc * s);
+  // i dn (c + i s) = (-dn s, dn c)
+  b[n + i] = mk(-sc * dn * s, sc * dn * c);
+}
+
+__global__ void k_bessel(int n, const double* __restrict__ z, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const JY01 r = jy01(z[i]);
+  out[5 * i + 0] = r.j0;
+  out[5 * i + 1] = r.y0;
+  out[5 * i + 2] = r.j1;
+  out[5 * i + 3] = r.y1;
+  out[5 * i + 4] = r.y1r;
+}
+
+// Direct FP64 product y = A x without storing A: one thread per row of the
+// 2N x 2N system, summing over all source nodes.
+__global__ __launch_bounds__(256) void k_matvec_direct(PointsDev P, MediumDev md, const cplx* __restrict__ x,
+                                                       cplx* __restrict__ y) {
+  const int n = P.n_boundary;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cplx y1 = mk(0, 0), y2 = mk(0, 0);
+  for (int j = 0; j < n; ++j) {
+    cplx e[4];
+    muller_pair(P, md, i, j, e);
+    const cplx xq = x[j], xu = x[n + j];
+    fma_acc(y1, e[0], xq);
+    fma_acc(y1, e[1], xu);
+    fma_acc(y2, e[2], xq);
+    fma_acc(y2, e[3], xu);
+  }
+  y[i] = y1;
+  y[n + i] = y2;
+}
+
+void launch_kblock(hipStream_t st, const PointsDev& P, const MediumDev& md, const KJob* jobs, const KTile* tiles,
+                   int ntiles, const int* rpt, const int* rmap1, const int* rmap2, const int* cpt,
+                   const int* cmap1, const int* cmap2) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_kblock, dim3(ntiles), dim3(256), 0, st, P, md, jobs, tiles, rpt, rmap1, rmap2, cpt,
+                     cmap1, cmap2);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_geometry(hipStream_t st, int n, const double* x, const double* dx, const double* ddx, double* px,
+                     double* py, double* nx, double* ny, double* w, double* kappa) {
+  hipLaunchKernelGGL(k_geometry, dim3(cdiv_int(n, 256)), dim3(256), 0, st, n, x, dx, ddx, px, py, nx, ny, w,
+                     kappa);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_rhs_plane(hipStream_t st, int n, const PointsDev& P, const MediumDev& md, double angle, cplx* b) {
+  hipLaunchKernelGGL(k_rhs_plane, dim3(cdiv_int(n, 256)), dim3(256), 0, st, n, P, md, cos(angle), sin(angle), b);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_bessel(hipStream_t st, int n, const double* z, double* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_bessel, dim3(cdiv_int(n, 256)), dim3(256), 0, st, n, z, out);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_matvec_direct(hipStream_t st, const PointsDev& P, const MediumDev& md, const cplx* x, cplx* y) {
+  hipLaunchKernelGGL(k_matvec_direct, dim3(cdiv_int(P.n_boundary, 256)), dim3(256), 0, st, P, md, x, y);
+  HIPCHK(hipGetLastError());
+}
+
+}  // namespace symhss
