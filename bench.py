@@ -1,0 +1,190 @@
+"""Benchmark: HSS compress + factor + solve of the symmetric Muller-like system on one GPU.
+
+A step is one pass of the whole path over one boundary: proxy-method
+compression (kernel blocks + IDs), factorisation (kernel blocks + LU) and one
+solve, with the boundary geometry and right-hand side already in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--config 2] [--no-base] [--no-cpu]
+
+Prints one JSON line.  Workload (default): star r = 1 + 0.3 cos 5t,
+N = 32768 nodes (65536 unknowns), k = 50 / 75, leaf 128, tol 1e-10.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_FP64_TFLOPS = 78.6
+MI355X_HBM_TBS = 8.0
+
+
+def _workload(cfg: int):
+    import workloads
+    if cfg == 1:
+        return workloads.config1()
+    if cfg == 2:
+        return workloads.config2()
+    if cfg == 4:
+        return workloads.config4()
+    raise SystemExit(f"unknown config {cfg}")
+
+
+def _run_form(s, wl, form, steps, warmup, b, x, torch):
+    x_, dx_, ddx_ = wl.boundary()
+    s.assemble(x_, dx_, ddx_, wl.k0, wl.k1, wl.eps0, wl.eps1, leaf=wl.leaf, tol=wl.tol, form=form,
+               n_proxy=wl.n_proxy if wl.n_proxy > 0 else 64, proxy_ratio=wl.proxy_ratio)
+    s.rhs_plane_wave_device(wl.angle, b.data_ptr())
+    for _ in range(warmup):
+        s.compress()
+        s.factor()
+        s.solve_device(b.data_ptr(), x.data_ptr())
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        s.compress()
+        s.factor()
+        s.solve_device(b.data_ptr(), x.data_ptr())
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - ts)
+    t1 = time.perf_counter()
+    return (t1 - t0) / max(steps, 1), s.stats(), per
+
+
+def _cpu_baseline(wl):
+    """The oracle on the host: dense assembly rows and dense LU on samples,
+    scaled to one dense solve of the full 2N system."""
+    import numpy as np
+    from oracle import dense, geometry, kernels
+    from oracle.kernels import Medium, PointSet
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    x, dx, ddx = wl.boundary()
+    g = geometry.discretize(x, dx, ddx)
+    med = Medium(wl.k0, wl.k1, wl.eps0, wl.eps1)
+    n = g.n
+    rows = 256
+    ps = PointSet.boundary(g)
+    t0 = time.perf_counter()
+    kernels.muller_blocks(ps.take(np.arange(rows)), ps, med, True)
+    t_rows = time.perf_counter() - t0
+    t_assembly = t_rows * n / rows  # all 2N x 2N entries (4 per node pair)
+    m = 3072
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    bb = rng.standard_normal(m) + 0j
+    t0 = time.perf_counter()
+    dense.solve_dense(A, bb)
+    t_lu = time.perf_counter() - t0
+    t_lu_full = t_lu * (2 * n / m) ** 3
+    total = t_assembly + t_lu_full
+    return {
+        "value": round(total, 3), "unit": "s/solve", "cores": int(cores), "kind": "oracle",
+        "sample": (f"oracle dense assembly of {rows} of {n} node rows (x{n / rows:.0f}) plus "
+                   f"scipy LU of a {m}x{m} complex system (x{(2 * n / m) ** 3:.0f} by n^3), "
+                   f"extrapolated to the dense {2 * n}-unknown solve; assembly {t_assembly:.1f} s, "
+                   f"LU {t_lu_full:.1f} s"),
+        "gentries_per_s": round(4.0 * rows * n / t_rows / 1e9, 5),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-base", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-residual", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this path has no multi-GPU mode); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2609_33216_amd import binding
+
+    wl = _workload(args.config)
+    n = wl.n
+    dev = torch.device("cuda:0")
+    b = torch.zeros(2 * n, dtype=torch.complex128, device=dev)
+    x = torch.zeros(2 * n, dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()  # the solver queues on its own stream
+    s = binding.Solver(0)
+
+    t_sym, st, per = _run_form(s, wl, binding.MULLER_SYM, args.steps, args.warmup, b, x, torch)
+    resid = None
+    if not args.no_residual:
+        y = torch.zeros_like(x)
+        torch.cuda.synchronize()
+        s.lib.symhss_matvec_direct(s.h, binding.ctypes.c_void_p(x.data_ptr()), binding.ctypes.c_void_p(y.data_ptr()),
+                                   binding.DEVICE_PTRS)
+        torch.cuda.synchronize()
+        resid = float(torch.linalg.vector_norm(y - b) / torch.linalg.vector_norm(b))
+
+    ent = st["entries_compress"] + st["entries_factor"]
+    t_kb = st["t_kblock_compress"] + st["t_kblock_factor"]
+    kernels_t = {"kblock": t_kb, "id": st["t_id"], "lu": st["t_lu"]}
+    out = {
+        "metric": "HSS compress+factor s/solve & Gentries/s, sym vs nonsym, at 1e-8 rel err",
+        "value": round(t_sym, 6),
+        "unit": "s/solve",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_sym, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "curve": f"{wl.curve} {dict(wl.curve_params)}", "n_nodes": n,
+                   "unknowns": 2 * n, "k_out": wl.k0, "k_in": wl.k1, "leaf": wl.leaf, "tol": wl.tol,
+                   "form": "symmetric one-sided ID", "parallelism": "1 GPU"},
+        "t_compress": round(st["t_compress"], 6),
+        "t_factor": round(st["t_factor"], 6),
+        "t_solve": round(st["t_solve"], 6),
+        "step_times": [round(v, 6) for v in per],
+        "entries": int(ent),
+        "gentries_per_s": round(ent / t_kb / 1e9, 3) if t_kb > 0 else None,
+        "kernel_seconds": {k: round(v, 6) for k, v in kernels_t.items()},
+        "ranks_max_per_level": st["rank_max"],
+        "root_size": st["root_size"],
+        "residual_fp64_direct": resid,
+    }
+    # roofline of the kernel-block generator: entries are written once to HBM (16 B each)
+    if t_kb > 0:
+        # (bytes per launch) / (mean launch duration) = total bytes / total kernel time
+        bw = ent * 16.0 / t_kb / 1e9
+        out["roofline"] = {"kernel": "k_kblock", "bound": "hbm", "achieved": round(bw, 2),
+                           "peak": MI355X_HBM_TBS * 1e3, "unit": "GB/s",
+                           "frac": round(bw / (MI355X_HBM_TBS * 1e3), 4), "traffic": None}
+
+    if not args.no_base:
+        t_base, stb, _ = _run_form(s, wl, binding.MULLER_BASE, 1, 1, b, x, torch)
+        out["nonsym"] = {"s_per_solve": round(t_base, 6), "t_compress": round(stb["t_compress"], 6),
+                         "t_factor": round(stb["t_factor"], 6),
+                         "entries": int(stb["entries_compress"] + stb["entries_factor"])}
+        out["speedup_sym_vs_nonsym"] = {"compress": round(stb["t_compress"] / st["t_compress"], 3),
+                                        "total": round(t_base / t_sym, 3)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = _cpu_baseline(wl)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

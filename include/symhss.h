@@ -67,7 +67,10 @@ typedef struct {
   int32_t form;        /* symhss_form */
   double tol;          /* relative ID tolerance: rank = #{j : |R_jj| > tol |R_00|}, > 0 */
   int32_t n_proxy;     /* minimum proxy points per circle (e.g. 64) */
-  int32_t pad0;
+  int32_t root_max;    /* top of the tree: compression stops at the first level (from the
+                          leaves) whose boxes' ranks sum to at most root_max, and that level's
+                          compressed system is factored densely; 0: default 1536; < 0: compress
+                          every level down to level 1 (two boxes at the root) */
   double proxy_ratio;  /* proxy radius / box radius (e.g. 1.5) */
 } symhss_opts;
 
@@ -133,7 +136,7 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
 typedef struct {
   int32_t levels;            /* L */
   int32_t leaf_boxes;        /* 2^L */
-  int32_t root_size;         /* order of the root system */
+  int32_t root_size;         /* order of the dense top-level system */
   int32_t form;
   int64_t entries_compress;  /* matrix entries generated by compress */
   int64_t entries_factor;    /* matrix entries generated by factor */
@@ -144,6 +147,8 @@ typedef struct {
   int32_t rank_min[32], rank_max[32]; /* per level (index = level), q + u rank of a box */
   double rank_mean[32];
   int32_t proxy_max[32];     /* largest proxy count per level */
+  int32_t n_kblock, n_id, n_lu;  /* timed launch groups behind t_kblock_*, t_id, t_lu */
+  int32_t root_level;        /* level whose boxes form the dense top-level system */
 } symhss_stats;
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);

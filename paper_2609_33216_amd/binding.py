@@ -36,7 +36,7 @@ class Medium(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("form", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("n_proxy", ctypes.c_int32), ("pad0", ctypes.c_int32), ("proxy_ratio", ctypes.c_double)]
+                ("n_proxy", ctypes.c_int32), ("root_max", ctypes.c_int32), ("proxy_ratio", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -48,10 +48,13 @@ class Stats(ctypes.Structure):
                 ("t_id", ctypes.c_double), ("t_lu", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64),
                 ("rank_min", ctypes.c_int32 * 32), ("rank_max", ctypes.c_int32 * 32),
-                ("rank_mean", ctypes.c_double * 32), ("proxy_max", ctypes.c_int32 * 32)]
+                ("rank_mean", ctypes.c_double * 32), ("proxy_max", ctypes.c_int32 * 32),
+                ("n_kblock", ctypes.c_int32), ("n_id", ctypes.c_int32), ("n_lu", ctypes.c_int32),
+                ("root_level", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("rank") and f != "proxy_max"}
+        d = {f: getattr(self, f) for f, _ in self._fields_
+             if not f.startswith("rank") and f != "proxy_max"}
         L = self.levels
         d["rank_min"] = list(self.rank_min[1:L + 1])
         d["rank_max"] = list(self.rank_max[1:L + 1])
@@ -153,7 +156,7 @@ class Solver:
     # -- main verbs ------------------------------------------------------
     def assemble(self, x, dx, ddx, k0: float, k1: float, eps0: float = 1.0, eps1: float | None = None,
                  leaf: int = 128, tol: float = 1e-10, form: int = MULLER_SYM, n_proxy: int = 64,
-                 proxy_ratio: float = 1.5):
+                 proxy_ratio: float = 1.5, root_max: int = 0):
         x = np.ascontiguousarray(x, dtype=np.float64)
         dx = np.ascontiguousarray(dx, dtype=np.float64)
         ddx = np.ascontiguousarray(ddx, dtype=np.float64)
@@ -162,7 +165,7 @@ class Solver:
         if eps1 is None:
             eps1 = (k1 / k0) ** 2 * eps0
         med = Medium(k0, k1, eps0, eps1)
-        opt = Opts(leaf, form, tol, n_proxy, 0, proxy_ratio)
+        opt = Opts(leaf, form, tol, n_proxy, root_max, proxy_ratio)
         self._check(self.lib.symhss_assemble(self.h, x.shape[0], _ptr(x), _ptr(dx), _ptr(ddx),
                                              ctypes.byref(med), ctypes.byref(opt)))
         self.n = x.shape[0]

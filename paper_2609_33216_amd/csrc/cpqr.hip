@@ -21,6 +21,7 @@ namespace symhss {
 
 
 constexpr int kIdThreads = 256;
+constexpr int kRegRows = 8;  // register-cached column segment: up to 512 rows
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -155,25 +156,56 @@ __global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ 
     }
     __syncthreads();
     const double tau = s_tau;
-    // apply to trailing columns, recompute their norms below row j
+    // apply to trailing columns, recompute their norms below row j; a column
+    // segment of up to kRegRows * 64 rows is read once into registers
+    const int rows = m - j;
     for (int c = j + 1 + wave; c < n; c += nwaves) {
-      cplx* col = D.A + ld * c;
-      cplx w = mk(0, 0);
-      for (int i = j + lane; i < m; i += 64) fma_conj_acc(w, v[i], col[i]);
-      w.re = wave_sum(w.re);
-      w.im = wave_sum(w.im);
-      const cplx tw = tau * w;
-      double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) {
-        cplx a = col[i];
-        const cplx vi = v[i];
-        a.re -= vi.re * tw.re - vi.im * tw.im;
-        a.im -= vi.re * tw.im + vi.im * tw.re;
-        col[i] = a;
-        if (i > j) s += abs2(a);
+      cplx* col = D.A + ld * c + j;
+      const cplx* vj = v + j;
+      if (rows <= kRegRows * 64) {
+        cplx a[kRegRows];
+        cplx w = mk(0, 0);
+#pragma unroll
+        for (int q = 0; q < kRegRows; ++q) {
+          const int i = lane + 64 * q;
+          a[q] = i < rows ? col[i] : mk(0, 0);
+          if (i < rows) fma_conj_acc(w, vj[i], a[q]);
+        }
+        w.re = wave_sum(w.re);
+        w.im = wave_sum(w.im);
+        const cplx tw = tau * w;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kRegRows; ++q) {
+          const int i = lane + 64 * q;
+          if (i < rows) {
+            const cplx vi = vj[i];
+            a[q].re -= vi.re * tw.re - vi.im * tw.im;
+            a[q].im -= vi.re * tw.im + vi.im * tw.re;
+            col[i] = a[q];
+            if (i > 0) s += abs2(a[q]);
+          }
+        }
+        s = wave_sum(s);
+        if (lane == 0) vn[c] = s;
+      } else {
+        cplx w = mk(0, 0);
+        for (int i = lane; i < rows; i += 64) fma_conj_acc(w, vj[i], col[i]);
+        w.re = wave_sum(w.re);
+        w.im = wave_sum(w.im);
+        const cplx tw = tau * w;
+        double s = 0.0;
+        for (int i = lane; i < rows; i += 64) {
+          cplx a = col[i];
+          const cplx vi = vj[i];
+          a.re -= vi.re * tw.re - vi.im * tw.im;
+          a.im -= vi.re * tw.im + vi.im * tw.re;
+          col[i] = a;
+          if (i > 0) s += abs2(a);
+        }
+        s = wave_sum(s);
+        if (lane == 0) vn[c] = s;
       }
-      s = wave_sum(s);
-      if (lane == 0) vn[c] = s;
     }
     __syncthreads();
   }

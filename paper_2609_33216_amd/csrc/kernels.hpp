@@ -91,6 +91,8 @@ void launch_equalise_ranks(hipStream_t st, int npairs, const int* ia, const int*
 
 // batched dense algebra (dense.hip)
 void launch_lu_fused(hipStream_t st, const LuDesc* d, int count);
+// host-looped multi-workgroup variant; nmax / ncolmax / nrhsmax bound n, ncol, ncol - n
+void launch_lu_multi(hipStream_t st, const LuDesc* d, int count, int nmax, int ncolmax, int nrhsmax);
 void launch_gemm_batched(hipStream_t st, const GemmDesc* d, int count, int mmax, int nmax);
 void launch_lu_solve(hipStream_t st, const SolveDesc* d, int count);
 void launch_copy_batched(hipStream_t st, const CopyDesc* d, int count, long maxelems);

@@ -148,6 +148,7 @@ class Solver {
              const std::vector<int>& c2);
   };
   void run_kblock(KBatch& kb, int timer_kind);
+  void root_block_jobs(KBatch& kb, cplx* out, int ld, const std::vector<int>& offs);
   PointsDev points() const;
   void upload_proxies(const std::vector<double>& px, const std::vector<double>& py,
                       const std::vector<double>& nx, const std::vector<double>& ny,
@@ -171,7 +172,9 @@ class Solver {
   MediumDev md_{};
   bool two_sided_ = false;
   int L_ = 0;
+  int root_level_ = 1;      // level whose compressed system is factored densely
   std::vector<Level> lev_;  // index = level 0..L
+  DBuf<int> rootmap_;       // per box of the root level: positions of its unknowns in the root system
   DBuf<cplx> scratch_;      // proxy matrices of one level
   DBuf<IdDesc> iddesc_;
   DBuf<int> idint_;

@@ -7,12 +7,13 @@ from oracle import dense, geometry, kernels
 from oracle.kernels import Medium
 
 
-def make_solver(wl, form=0, leaf=None, tol=None, n_proxy=None):
+def make_solver(wl, form=0, leaf=None, tol=None, n_proxy=None, root_max=0):
     from paper_2609_33216_amd import binding
     x, dx, ddx = wl.boundary()
     s = binding.Solver(0)
     s.assemble(x, dx, ddx, wl.k0, wl.k1, wl.eps0, wl.eps1, leaf=leaf or wl.leaf, tol=tol or wl.tol, form=form,
-               n_proxy=n_proxy or (wl.n_proxy if wl.n_proxy > 0 else 64), proxy_ratio=wl.proxy_ratio)
+               n_proxy=n_proxy or (wl.n_proxy if wl.n_proxy > 0 else 64), proxy_ratio=wl.proxy_ratio,
+               root_max=root_max)
     return s
 
 

@@ -14,10 +14,10 @@ from tests.gpu_common import make_solver, oracle_system, rel
 pytestmark = pytest.mark.gpu
 
 
-def _run(wl, form, nrhs=1):
+def _run(wl, form, nrhs=1, root_max=0):
     row_scaled = form != 1
     g, med, A, b = oracle_system(wl, row_scaled)
-    s = make_solver(wl, form=form)
+    s = make_solver(wl, form=form, root_max=root_max)
     bd = s.rhs_plane_wave(wl.angle)
     assert rel(bd, b) < 1e-14
     s.compress()
@@ -32,15 +32,19 @@ def _run(wl, form, nrhs=1):
         x = s.solve(B)
         xd = dense.solve_dense(A, B)
     st = s.stats()
-    print(wl.name, "form", form, "err", rel(x, xd), "ranks", st["rank_max"], "root", st["root_size"])
+    print(wl.name, "form", form, "err", rel(x, xd), "ranks", st["rank_max"], "root", st["root_size"],
+          "at level", st["root_level"])
     return rel(x, xd), st
 
 
+@pytest.mark.parametrize("root_max", [0, -1])
 @pytest.mark.parametrize("form", [0, 1, 2])
-def test_circle_config1_shape(form):
+def test_circle_config1_shape(form, root_max):
     wl = workloads.config1()
-    err, st = _run(wl, form)
+    err, st = _run(wl, form, root_max=root_max)
     assert err < 1e-8
+    if root_max < 0:
+        assert st["root_level"] == 1
 
 
 def test_star_small_ragged():
@@ -49,9 +53,10 @@ def test_star_small_ragged():
     assert err < 1e-8
 
 
-def test_star_reduced_config2():
+@pytest.mark.parametrize("form", [0, 1])
+def test_star_reduced_config2(form):
     wl = workloads.config2_reduced(4096)
-    err, _ = _run(wl, 0)
+    err, _ = _run(wl, form)
     assert err < 1e-8
 
 
