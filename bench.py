@@ -166,13 +166,32 @@ def main():
         "root_size": st["root_size"],
         "residual_fp64_direct": resid,
     }
-    # roofline of the kernel-block generator: entries are written once to HBM (16 B each)
+    # Rooflines.  achieved = algorithmic work of the timed launches / their
+    # summed duration (HIP events on the solver's stream), i.e. the mean work
+    # per launch over the mean launch time.  The kernel-block generator is
+    # priced by the bytes of the entries it writes (16 B each) against HBM;
+    # the ID and LU kernels by FP64 flops against the FP64 peak.
+    rl = {}
     if t_kb > 0:
-        # (bytes per launch) / (mean launch duration) = total bytes / total kernel time
-        bw = ent * 16.0 / t_kb / 1e9
-        out["roofline"] = {"kernel": "k_kblock", "bound": "hbm", "achieved": round(bw, 2),
-                           "peak": MI355X_HBM_TBS * 1e3, "unit": "GB/s",
-                           "frac": round(bw / (MI355X_HBM_TBS * 1e3), 4), "traffic": None}
+        a = st["bytes_kblock"] / t_kb / 1e9
+        rl["k_kblock"] = {"bound": "hbm", "achieved": a, "peak": MI355X_HBM_TBS * 1e3, "unit": "GB/s",
+                          "seconds": t_kb, "launches": st["n_kblock"]}
+    for name, t, f, nl in (("k_cpqr", st["t_id"], st["flops_id"], st["n_id"]),
+                           ("k_lu_fused", st["t_lu_batched"], st["flops_lu_batched"], st["n_lu_batched"]),
+                           ("lu_multi", st["t_lu_multi"], st["flops_lu_multi"], st["n_lu_multi"])):
+        if t > 0:
+            rl[name] = {"bound": "alu", "achieved": f / t / 1e12, "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "seconds": t, "launches": nl}
+    for v in rl.values():
+        v["frac"] = round(v["achieved"] / v["peak"], 4)
+        v["achieved"] = round(v["achieved"], 3)
+        v["seconds"] = round(v["seconds"], 6)
+    if rl:
+        dom = max(rl, key=lambda k: rl[k]["seconds"])
+        d = rl[dom]
+        out["roofline"] = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+                           "unit": d["unit"], "frac": d["frac"], "traffic": None}
+        out["kernel_rooflines"] = rl
 
     if not args.no_base:
         t_base, stb, _ = _run_form(s, wl, binding.MULLER_BASE, 1, 1, b, x, torch)

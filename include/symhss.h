@@ -147,8 +147,15 @@ typedef struct {
   int32_t rank_min[32], rank_max[32]; /* per level (index = level), q + u rank of a box */
   double rank_mean[32];
   int32_t proxy_max[32];     /* largest proxy count per level */
-  int32_t n_kblock, n_id, n_lu;  /* timed launch groups behind t_kblock_*, t_id, t_lu */
+  int32_t n_kblock, n_id, n_lu;  /* timed launches behind t_kblock_*, t_id, t_lu */
   int32_t root_level;        /* level whose boxes form the dense top-level system */
+  /* algorithmic work of the timed launches (FP64 real flops; bytes written) */
+  double flops_id;           /* pivoted QR steps and T = R11^-1 R12 of the IDs */
+  double flops_lu_batched;   /* one-workgroup-per-block LU launches (k_lu_fused) */
+  double flops_lu_multi;     /* multi-workgroup LU (top levels and the dense top system) */
+  double t_lu_batched, t_lu_multi;  /* seconds, HIP events; t_lu = their sum */
+  int32_t n_lu_batched, n_lu_multi;
+  double bytes_kblock;       /* 16 bytes per generated entry (compress + factor) */
 } symhss_stats;
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);

@@ -50,7 +50,11 @@ class Stats(ctypes.Structure):
                 ("rank_min", ctypes.c_int32 * 32), ("rank_max", ctypes.c_int32 * 32),
                 ("rank_mean", ctypes.c_double * 32), ("proxy_max", ctypes.c_int32 * 32),
                 ("n_kblock", ctypes.c_int32), ("n_id", ctypes.c_int32), ("n_lu", ctypes.c_int32),
-                ("root_level", ctypes.c_int32)]
+                ("root_level", ctypes.c_int32),
+                ("flops_id", ctypes.c_double), ("flops_lu_batched", ctypes.c_double),
+                ("flops_lu_multi", ctypes.c_double), ("t_lu_batched", ctypes.c_double),
+                ("t_lu_multi", ctypes.c_double), ("n_lu_batched", ctypes.c_int32),
+                ("n_lu_multi", ctypes.c_int32), ("bytes_kblock", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_

@@ -20,7 +20,6 @@
 namespace symhss {
 
 
-constexpr int kIdThreads = 256;
 constexpr int kRegRows = 8;  // register-cached column segment: up to 512 rows
 
 __device__ inline double wave_sum(double v) {
@@ -29,6 +28,7 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+template <int kIdThreads>
 __global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ descs, double tol, int want_T) {
   extern __shared__ double lds[];
   const IdDesc D = descs[blockIdx.x];
@@ -264,14 +264,19 @@ __global__ void k_equalise_ranks(int npairs, const int* __restrict__ ia, const i
 }
 
 size_t cpqr_lds_bytes(int mmax, int nmax) {
-  return sizeof(double) * (size_t)nmax + sizeof(cplx) * (size_t)mmax + 4 * (sizeof(double) + sizeof(int)) + 64;
+  return sizeof(double) * (size_t)nmax + sizeof(cplx) * (size_t)mmax + 16 * (sizeof(double) + sizeof(int)) + 64;
 }
 
 void launch_cpqr(hipStream_t st, const IdDesc* descs, int count, int mmax, int nmax, double tol, int want_T) {
   if (count <= 0) return;
   const size_t lds = cpqr_lds_bytes(mmax, nmax);
   if (lds > 160 * 1024) throw std::runtime_error("proxy matrix too large for the ID kernel's LDS staging");
-  hipLaunchKernelGGL(k_cpqr, dim3(count), dim3(kIdThreads), lds, st, descs, tol, want_T);
+  // many matrices: 4 wavefronts each, several workgroups per CU; few (large)
+  // matrices: 16 wavefronts per workgroup to keep the CU's memory pipe busy
+  if (count >= 128)
+    hipLaunchKernelGGL(k_cpqr<256>, dim3(count), dim3(256), lds, st, descs, tol, want_T);
+  else
+    hipLaunchKernelGGL(k_cpqr<1024>, dim3(count), dim3(1024), lds, st, descs, tol, want_T);
   HIPCHK(hipGetLastError());
 }
 

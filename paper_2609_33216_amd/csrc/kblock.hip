@@ -21,6 +21,11 @@
 
 namespace symhss {
 
+// The Bessel evaluation is kept out of line: inlined twice (one per
+// wavenumber) the compiler interleaves the two and the register count
+// doubles, costing occupancy.
+__device__ __noinline__ JY01 jy01_call(double z) { return jy01(z); }
+
 __device__ inline void muller_pair(const PointsDev& P, const MediumDev& md, int io, int is,
                                    cplx e[4]) {
   const double e0 = md.eps0, e1 = md.eps1;
@@ -49,8 +54,8 @@ __device__ inline void muller_pair(const PointsDev& P, const MediumDev& md, int 
   const double dno = dx * P.nx[io] + dy * P.ny[io];
   const double dns = dx * P.nx[is] + dy * P.ny[is];
   const double nn = P.nx[io] * P.nx[is] + P.ny[io] * P.ny[is];
-  const JY01 a = jy01(md.k0 * r);
-  const JY01 b = jy01(md.k1 * r);
+  const JY01 a = jy01_call(md.k0 * r);
+  const JY01 b = jy01_call(md.k1 * r);
   const double k0 = md.k0, k1 = md.k1;
   const double pole = kTwoOverPi * invr;  // 2/(pi r)
   // A11: -(i/4) (eps0^2 H0a - eps1^2 H0b) * om
@@ -101,6 +106,7 @@ __global__ __launch_bounds__(256) void k_kblock(PointsDev P, MediumDev md, const
   const int o1 = rmap1[J.roff + a];
   const int o2 = rmap2[J.roff + a];
   const long ld = J.ld;
+#pragma unroll 1
   for (int cc = slot; cc < 16; cc += 4) {
     const int b = t.c0 + cc;
     if (b >= J.nc) break;

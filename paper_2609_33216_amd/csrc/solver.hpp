@@ -105,7 +105,8 @@ struct Level {
 
 struct TimerPair {
   hipEvent_t a, b;
-  int what;  // 0 kblock-compress, 1 kblock-factor, 2 id, 3 lu
+  int what;      // 0 kblock-compress, 1 kblock-factor, 2 id, 3 lu batched, 4 lu multi
+  double work;   // algorithmic flops (or bytes for kblock) of the timed launch
 };
 
 class Solver {
@@ -153,7 +154,7 @@ class Solver {
   void upload_proxies(const std::vector<double>& px, const std::vector<double>& py,
                       const std::vector<double>& nx, const std::vector<double>& ny,
                       const std::vector<double>& w);
-  void timer_begin(int what);
+  void timer_begin(int what, double work = 0.0);
   void timer_end();
   void collect_timers();
   void sync();
