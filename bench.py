@@ -24,6 +24,32 @@ sys.path.insert(0, ROOT)
 MI355X_FP64_TFLOPS = 78.6
 MI355X_HBM_TBS = 8.0
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs of
+# this script (star5-n32768-k50-75, one step), scaled by the same counters read
+# on a plain 512 MiB copy (fetch x2.0, write x1.0).  Valid only while the
+# kernel's source is the one profiled: keyed by the SHA-256 prefix of its file.
+MEASURED_TRAFFIC = {
+    "k_cpqr": {"source": "cpqr.hip", "sha": "bc2af5c2f8b06665", "bytes": 2.5617e9,
+               "profile": "profiles/k_cpqr_star5-n32768.md"},
+    "k_lu_fused": {"source": "dense.hip", "sha": "68e391844583578b", "bytes": 0.76656e9,
+                   "profile": "profiles/k_lu_fused_star5-n32768.md"},
+    "k_kblock": {"source": "kblock.hip", "sha": "20fba2554b30b7fb", "bytes": 0.062492e9,
+                 "profile": "profiles/k_kblock_star5-n32768.md"},
+}
+
+
+def _traffic(kernel: str, workload: str):
+    import hashlib
+    t = MEASURED_TRAFFIC.get(kernel)
+    if t is None or workload != "star5-n32768-k50-75":
+        return None
+    src = os.path.join(ROOT, "paper_2609_33216_amd", "csrc", t["source"])
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return t["bytes"] if sha == t["sha"] else None
+
 
 def _workload(cfg: int):
     import workloads
@@ -178,7 +204,7 @@ def main():
                           "seconds": t_kb, "launches": st["n_kblock"]}
     for name, t, f, nl in (("k_cpqr", st["t_id"], st["flops_id"], st["n_id"]),
                            ("k_lu_fused", st["t_lu_batched"], st["flops_lu_batched"], st["n_lu_batched"]),
-                           ("lu_multi", st["t_lu_multi"], st["flops_lu_multi"], st["n_lu_multi"])):
+                           ("lu_multi (several kernels)", st["t_lu_multi"], st["flops_lu_multi"], st["n_lu_multi"])):
         if t > 0:
             rl[name] = {"bound": "alu", "achieved": f / t / 1e12, "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
                         "seconds": t, "launches": nl}
@@ -186,11 +212,14 @@ def main():
         v["frac"] = round(v["achieved"] / v["peak"], 4)
         v["achieved"] = round(v["achieved"], 3)
         v["seconds"] = round(v["seconds"], 6)
-    if rl:
-        dom = max(rl, key=lambda k: rl[k]["seconds"])
+    single = [k for k in ("k_kblock", "k_cpqr", "k_lu_fused") if k in rl]
+    if single:
+        # the single kernel with the most event time per step
+        dom = max(single, key=lambda k: rl[k]["seconds"])
         d = rl[dom]
         out["roofline"] = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
-                           "unit": d["unit"], "frac": d["frac"], "traffic": None}
+                           "unit": d["unit"], "frac": d["frac"], "traffic": _traffic(dom, wl.name),
+                           "avg_launch_us": round(1e6 * d["seconds"] / max(d["launches"], 1), 1)}
         out["kernel_rooflines"] = rl
 
     if not args.no_base:
