@@ -13,6 +13,12 @@
  * decomposition; with symmetry one ID per half-box serves as left and right
  * basis (eq. low-rank_R).
  *
+ * A context may also hold a batch of boundaries (symhss_assemble_batch): the
+ * boundaries are independent problems, each with its own medium, and every
+ * tree level of all of them is compressed and factored in the same launches.
+ * The unknowns of boundary t then occupy [2 B_t, 2 B_t + 2 N_t), with
+ * B_t = N_0 + ... + N_{t-1}, each block in the order [q; u].
+ *
  * Calling order: create -> assemble -> compress -> factor -> solve (any
  * number of times).  assemble invalidates later stages; calls out of order
  * return SYMHSS_ESTATE.  Every call returns a status and never aborts; the
@@ -96,6 +102,16 @@ void *symhss_stream(symhss_ctx *ctx);
 symhss_status symhss_assemble(symhss_ctx *ctx, int64_t n, const double *x, const double *dx, const double *ddx,
                               const symhss_medium *medium, const symhss_opts *opts);
 
+/* Batch of `count` independent boundaries (Section 4.1's partition per
+ * boundary; the boundaries do not interact).  n[t]: nodes of boundary t;
+ * x, dx, ddx: the boundaries' node arrays (as for symhss_assemble) one after
+ * another, sum(n) x 2 doubles each; media[t]: its materials.  One option set
+ * for all.  Levels are counted from the leaves of the deepest boundary.
+ * EINVAL as for symhss_assemble, per boundary. */
+symhss_status symhss_assemble_batch(symhss_ctx *ctx, int32_t count, const int64_t *n, const double *x,
+                                    const double *dx, const double *ddx, const symhss_medium *media,
+                                    const symhss_opts *opts);
+
 /* Proxy-method compression (Section 4.1), levels L..1: generates M_R (and
  * M_L for the two-sided forms) on the GPU and computes the column-pivoted
  * QR IDs of their halves. */
@@ -118,9 +134,15 @@ symhss_status symhss_solve(symhss_ctx *ctx, const symhss_z *b, symhss_z *x, int3
  * b = [-eps0 W u_in; W q_in] (eq. symmetric_muller) or [-eps0 u_in; q_in]. */
 symhss_status symhss_rhs_plane_wave(symhss_ctx *ctx, double angle, symhss_z *b, int32_t flags);
 
+/* Plane-wave right-hand sides of a batch: angles[t] for boundary t (the
+ * layout of symhss_solve).  symhss_rhs_plane_wave uses one angle for all. */
+symhss_status symhss_rhs_plane_wave_batch(symhss_ctx *ctx, const double *angles, symhss_z *b, int32_t flags);
+
 /* Verification: entries A[rows][:, cols] of the 2N x 2N system (indices
  * < N: first equation / q unknown of node i; N + i: second equation / u
- * unknown), out is nr x nc column-major, host memory.  Valid after assemble. */
+ * unknown), out is nr x nc column-major, host memory.  Valid after assemble.
+ * For a batch, indices are global unknowns and entries that couple two
+ * boundaries are zero. */
 symhss_status symhss_eval_entries(symhss_ctx *ctx, int64_t nr, const int64_t *rows, int64_t nc,
                                   const int64_t *cols, symhss_z *out);
 
@@ -129,14 +151,15 @@ symhss_status symhss_eval_entries(symhss_ctx *ctx, int64_t nr, const int64_t *ro
 symhss_status symhss_eval_bessel(symhss_ctx *ctx, int64_t n, const double *z, double *out);
 
 /* y = A x with every entry generated on the fly in FP64 (no storage; O(N^2)
- * work).  x, y: 2N complex; host pointers unless SYMHSS_DEVICE_PTRS. */
+ * work per boundary; block-diagonal for a batch).  x, y: 2N complex; host
+ * pointers unless SYMHSS_DEVICE_PTRS. */
 symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z *y, int32_t flags);
 
 /* Statistics of the last assemble/compress/factor/solve. */
 typedef struct {
   int32_t levels;            /* L */
   int32_t leaf_boxes;        /* 2^L */
-  int32_t root_size;         /* order of the dense top-level system */
+  int32_t root_size;         /* order of the dense top-level system (largest of a batch) */
   int32_t form;
   int64_t entries_compress;  /* matrix entries generated by compress */
   int64_t entries_factor;    /* matrix entries generated by factor */
@@ -148,7 +171,8 @@ typedef struct {
   double rank_mean[32];
   int32_t proxy_max[32];     /* largest proxy count per level */
   int32_t n_kblock, n_id, n_lu;  /* timed launches behind t_kblock_*, t_id, t_lu */
-  int32_t root_level;        /* level whose boxes form the dense top-level system */
+  int32_t root_level;        /* level whose boxes form the dense top-level system (batch: the
+                                highest such level) */
   /* algorithmic work of the timed launches (FP64 real flops; bytes written) */
   double flops_id;           /* pivoted QR steps and T = R11^-1 R12 of the IDs */
   double flops_lu_batched;   /* one-workgroup-per-block LU launches (k_lu_fused) */
@@ -160,7 +184,9 @@ typedef struct {
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);
 
-/* Verification: data of one box after compress.  `what` selects:
+/* Verification: data of one box after compress.  The box is the box-th of
+ * all boxes at `level` (boundaries of a batch one after another, each in
+ * curve order).  `what` selects:
  *  0/1  active column node ids (q / u half)      2/3  active row node ids (eq 1 / eq 2)
  *  4/5  column skeleton, local indices (q / u)    6/7  row skeleton, local indices
  *  8    dense column interpolation R (kc x sc, complex, column-major)
@@ -168,6 +194,9 @@ symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);
  *  10   proxy circle: centre x, centre y, radius, count (4 doubles)
  *  11/12 near row node ids (eq 1 / eq 2)          13/14 near column node ids (q / u)
  *  15   ranks kc_q, kc_u, kr_q, kr_u (4 int32)
+ *  16   boundary, index within the boundary's boxes at this level, first node,
+ *       one past the last node, 1 if the box is part of its boundary's dense
+ *       top-level system (5 int32)
  * Element type: int32 for ids/indices/ranks, symhss_z for 8/9, double for 10.
  * With out == NULL only *count is set; otherwise out must hold *count elements. */
 symhss_status symhss_box_query(symhss_ctx *ctx, int32_t level, int32_t box, int32_t what, int64_t *count,

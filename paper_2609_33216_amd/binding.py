@@ -71,6 +71,7 @@ EXPORTS = [
     "symhss_create", "symhss_destroy", "symhss_last_error", "symhss_stream", "symhss_assemble",
     "symhss_compress", "symhss_factor", "symhss_solve", "symhss_rhs_plane_wave", "symhss_eval_entries",
     "symhss_eval_bessel", "symhss_matvec_direct", "symhss_get_stats", "symhss_box_query",
+    "symhss_assemble_batch", "symhss_rhs_plane_wave_batch",
 ]
 
 _lib = None
@@ -108,6 +109,8 @@ def load(path: str | None = None):
         "symhss_matvec_direct": ([vp, vp, vp, i32], ctypes.c_int),
         "symhss_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
         "symhss_box_query": ([vp, i32, i32, i32, ctypes.POINTER(i64), vp], ctypes.c_int),
+        "symhss_assemble_batch": ([vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)], ctypes.c_int),
+        "symhss_rhs_plane_wave_batch": ([vp, vp, vp, i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -174,6 +177,37 @@ class Solver:
                                              ctypes.byref(med), ctypes.byref(opt)))
         self.n = x.shape[0]
 
+    def assemble_batch(self, boundaries, media, leaf: int = 128, tol: float = 1e-10, form: int = MULLER_SYM,
+                       n_proxy: int = 64, proxy_ratio: float = 1.5, root_max: int = 0):
+        """boundaries: list of (x, dx, ddx) arrays of shape (N_t, 2); media: list of
+        (k0, k1, eps0, eps1).  The unknowns of boundary t follow those of t-1."""
+        if len(boundaries) != len(media) or not boundaries:
+            raise ValueError("one medium per boundary")
+        ns = np.array([np.asarray(b[0]).shape[0] for b in boundaries], dtype=np.int64)
+        cat = []
+        for a in range(3):
+            arr = np.ascontiguousarray(np.concatenate([np.asarray(b[a], dtype=np.float64) for b in boundaries]))
+            if arr.ndim != 2 or arr.shape != (int(ns.sum()), 2):
+                raise ValueError("each of x, dx, ddx must be (N_t, 2)")
+            cat.append(arr)
+        meds = (Medium * len(media))(*[Medium(*m) for m in media])
+        opt = Opts(leaf, form, tol, n_proxy, root_max, proxy_ratio)
+        self._check(self.lib.symhss_assemble_batch(self.h, len(boundaries), _ptr(ns), _ptr(cat[0]), _ptr(cat[1]),
+                                                   _ptr(cat[2]), ctypes.cast(meds, ctypes.c_void_p),
+                                                   ctypes.byref(opt)))
+        self.n = int(ns.sum())
+        self.batch_n = [int(v) for v in ns]
+
+    def rhs_plane_wave_batch(self, angles):
+        a = np.ascontiguousarray(angles, dtype=np.float64)
+        b = np.zeros(2 * self.n, dtype=np.complex128)
+        self._check(self.lib.symhss_rhs_plane_wave_batch(self.h, _ptr(a), _ptr(b), 0))
+        return b
+
+    def rhs_plane_wave_batch_device(self, angles, b_ptr: int):
+        a = np.ascontiguousarray(angles, dtype=np.float64)
+        self._check(self.lib.symhss_rhs_plane_wave_batch(self.h, _ptr(a), ctypes.c_void_p(b_ptr), DEVICE_PTRS))
+
     def compress(self):
         self._check(self.lib.symhss_compress(self.h))
 
@@ -236,6 +270,8 @@ class Solver:
             out = np.zeros(n, dtype=np.complex128)
         elif what == 10:
             out = np.zeros(n, dtype=np.float64)
+        elif what == 16:
+            out = np.zeros(n, dtype=np.int32)
         else:
             out = np.zeros(n, dtype=np.int32)
         if n:

@@ -91,6 +91,13 @@ symhss_status symhss_assemble(symhss_ctx* ctx, int64_t n, const double* x, const
   return guarded(ctx, [&](symhss::Solver& s) { s.assemble(n, x, dx, ddx, *medium, *opts); });
 }
 
+symhss_status symhss_assemble_batch(symhss_ctx* ctx, int32_t count, const int64_t* n, const double* x,
+                                    const double* dx, const double* ddx, const symhss_medium* media,
+                                    const symhss_opts* opts) {
+  if (!opts || !n || !media || count < 1) return SYMHSS_EINVAL;
+  return guarded(ctx, [&](symhss::Solver& s) { s.assemble_batch(count, n, x, dx, ddx, media, *opts); });
+}
+
 symhss_status symhss_compress(symhss_ctx* ctx) {
   return guarded(ctx, [&](symhss::Solver& s) { s.compress(); });
 }
@@ -107,6 +114,13 @@ symhss_status symhss_rhs_plane_wave(symhss_ctx* ctx, double angle, symhss_z* b, 
   return guarded(ctx, [&](symhss::Solver& s) {
     if (!b) throw std::invalid_argument("null output");
     s.rhs_plane_wave(angle, b, flags);
+  });
+}
+
+symhss_status symhss_rhs_plane_wave_batch(symhss_ctx* ctx, const double* angles, symhss_z* b, int32_t flags) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    if (!b || !angles) throw std::invalid_argument("null argument");
+    s.rhs_plane_wave_batch(angles, b, flags);
   });
 }
 

@@ -46,7 +46,8 @@ __host__ __device__ inline cplx cdiv(cplx a, cplx b) {
 }
 
 // Boundary and proxy points, structure of arrays.  Index < n_boundary is a
-// boundary node; larger indices are proxy points of the current level.
+// boundary node (the nodes of all boundaries of a batch, one after another);
+// larger indices are proxy points of the current level.
 struct PointsDev {
   const double* x;
   const double* y;
@@ -81,7 +82,7 @@ struct KJob {
   int nr, nc;
   int roff, coff;  // offsets into the row / column index arrays
   int mode;
-  int pad;
+  int med;         // index of the medium (one per boundary of a batch)
 };
 
 struct KTile {

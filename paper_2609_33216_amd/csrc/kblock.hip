@@ -92,13 +92,15 @@ __device__ inline void muller_pair(const PointsDev& P, const MediumDev& md, int 
   }
 }
 
-__global__ __launch_bounds__(256) void k_kblock(PointsDev P, MediumDev md, const KJob* __restrict__ jobs,
+__global__ __launch_bounds__(256) void k_kblock(PointsDev P, const MediumDev* __restrict__ media,
+                                                const KJob* __restrict__ jobs,
                                                 const KTile* __restrict__ tiles,
                                                 const int* __restrict__ rpt, const int* __restrict__ rmap1,
                                                 const int* __restrict__ rmap2, const int* __restrict__ cpt,
                                                 const int* __restrict__ cmap1, const int* __restrict__ cmap2) {
   const KTile t = tiles[blockIdx.x];
   const KJob J = jobs[t.job];
+  const MediumDev md = media[J.med];
   const int a = t.r0 + (threadIdx.x & 63);
   const int slot = threadIdx.x >> 6;
   if (a >= J.nr) return;
@@ -196,11 +198,11 @@ __global__ __launch_bounds__(256) void k_matvec_direct(PointsDev P, MediumDev md
   y[n + i] = y2;
 }
 
-void launch_kblock(hipStream_t st, const PointsDev& P, const MediumDev& md, const KJob* jobs, const KTile* tiles,
-                   int ntiles, const int* rpt, const int* rmap1, const int* rmap2, const int* cpt,
-                   const int* cmap1, const int* cmap2) {
+void launch_kblock(hipStream_t st, const PointsDev& P, const MediumDev* media, const KJob* jobs,
+                   const KTile* tiles, int ntiles, const int* rpt, const int* rmap1, const int* rmap2,
+                   const int* cpt, const int* cmap1, const int* cmap2) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_kblock, dim3(ntiles), dim3(256), 0, st, P, md, jobs, tiles, rpt, rmap1, rmap2, cpt,
+  hipLaunchKernelGGL(k_kblock, dim3(ntiles), dim3(256), 0, st, P, media, jobs, tiles, rpt, rmap1, rmap2, cpt,
                      cmap1, cmap2);
   HIPCHK(hipGetLastError());
 }

@@ -74,9 +74,10 @@ struct SolveDesc {
 };
 
 // kernel-block generation (kblock.hip)
-void launch_kblock(hipStream_t st, const PointsDev& P, const MediumDev& md, const KJob* jobs, const KTile* tiles,
-                   int ntiles, const int* rpt, const int* rmap1, const int* rmap2, const int* cpt,
-                   const int* cmap1, const int* cmap2);
+// media: device array indexed by KJob::med
+void launch_kblock(hipStream_t st, const PointsDev& P, const MediumDev* media, const KJob* jobs,
+                   const KTile* tiles, int ntiles, const int* rpt, const int* rmap1, const int* rmap2,
+                   const int* cpt, const int* cmap1, const int* cmap2);
 void launch_geometry(hipStream_t st, int n, const double* x, const double* dx, const double* ddx, double* px,
                      double* py, double* nx, double* ny, double* w, double* kappa);
 void launch_rhs_plane(hipStream_t st, int n, const PointsDev& P, const MediumDev& md, double angle, cplx* b);

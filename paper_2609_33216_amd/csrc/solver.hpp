@@ -68,9 +68,17 @@ class Uploader {
   std::vector<Chunk> chunks_;
 };
 
+// Geometry of one box of a boundary's full binary tree.
+struct BoxGeom {
+  int lo = 0, hi = 0;  // node range (global node ids)
+  double cx = 0, cy = 0, rad = 0;
+};
+
 struct Box {
   int lo = 0, hi = 0;         // node range of the box
   double cx = 0, cy = 0, rad = 0;
+  int tree = 0;               // boundary of a batch
+  int li = 0;                 // index among its tree's boxes at this height
   std::vector<int> rows[2];   // active row node ids: first / second equation
   std::vector<int> cols[2];   // active column node ids: q / u unknowns
   std::vector<int> rsk[2];    // row skeleton: local indices into rows[h]
@@ -89,8 +97,12 @@ struct Box {
   size_t off_s = 0, off_k = 0;  // prefix sums of s and k (solve buffers, maps)
 };
 
+// All boxes at one height of the forest (height 0: leaves).  The boxes of a
+// tree are contiguous and in curve order, so the children of box li of tree t
+// at height h are boxes 2 li and 2 li + 1 of t at height h - 1.
 struct Level {
   std::vector<Box> boxes;
+  std::vector<int> tstart;  // per tree: index of its first box here, -1 if absent
   DBuf<cplx> interp;     // R and L of every box
   DBuf<cplx> aug1;       // [D | L] -> [LU(D) | X]
   DBuf<cplx> aug2;       // [R X | I] -> [LU | A~]
@@ -98,9 +110,24 @@ struct Level {
   DBuf<int> info;        // 2 per box
   DBuf<int> childmap;    // per box (levels >= 1): positions of its k unknowns in the parent
   DBuf<int> leafmap;     // leaves: global indices of the 2n local unknowns
+  DBuf<int> rootmap;     // boxes of trees whose dense top-level system is at this height:
+                         // positions of their unknowns in that system
   // solve buffers
   DBuf<cplx> F, G, Ft, Z;
   size_t s_total = 0, k_total = 0;
+};
+
+// One boundary of a batch (a single-boundary context holds one).
+struct Tree {
+  int64_t base = 0, n = 0;  // nodes [base, base + n); unknowns [2 base, 2 base + 2 n)
+  int L = 0;                // box-tree levels (leaves at level L, height 0)
+  symhss_medium med{};
+  MediumDev md{};
+  std::vector<std::vector<BoxGeom>> geom;  // per height, the full binary tree
+  int root_h = -1;          // height of the dense top-level system
+  int root_n = 0;           // its order
+  size_t root_off = 0;      // offset of its matrix in the root buffer
+  size_t rootvec_off = 0;   // offset of its unknowns in the root vectors
 };
 
 struct TimerPair {
@@ -116,10 +143,14 @@ class Solver {
 
   void assemble(int64_t n, const double* x, const double* dx, const double* ddx, const symhss_medium& med,
                 const symhss_opts& opts);
+  // count boundaries of n[t] nodes each, geometry arrays concatenated
+  void assemble_batch(int count, const int64_t* n, const double* x, const double* dx, const double* ddx,
+                      const symhss_medium* med, const symhss_opts& opts);
   void compress();
   void factor();
   void solve(const symhss_z* b, symhss_z* x, int nrhs, int flags);
   void rhs_plane_wave(double angle, symhss_z* b, int flags);
+  void rhs_plane_wave_batch(const double* angles, symhss_z* b, int flags);
   void eval_entries(int64_t nr, const int64_t* rows, int64_t nc, const int64_t* cols, symhss_z* out);
   void eval_bessel(int64_t n, const double* z, double* out);
   void matvec_direct(const symhss_z* x, symhss_z* y, int flags);
@@ -132,24 +163,30 @@ class Solver {
  private:
   // planning
   void build_tree();
-  void set_active(int l);
-  void plan_proxy_near(int l);
+  void set_active(int h);
+  void plan_proxy_near(int h);
+  void add_height(int h, const std::vector<int>& trees);
+  int level_of(int h) const { return Lmax_ - h; }
+  const Box& child(int h, const Box& B, int w) const {
+    return hev_[h - 1].boxes[hev_[h - 1].tstart[B.tree] + 2 * B.li + w];
+  }
   // compress pieces
-  void compress_level(int l);
+  void compress_level(int h);
   // factor pieces
-  void factor_level(int l);
+  void factor_level(int h);
   void factor_root();
   // kernel-block launches
   struct KBatch {
     std::vector<KJob> jobs;
     std::vector<int> rpt, rm1, rm2, cpt, cm1, cm2;
     int64_t entries = 0;
-    void add(cplx* out, int ld, int mode, const std::vector<int>& rp, const std::vector<int>& r1,
+    void add(cplx* out, int ld, int mode, int med, const std::vector<int>& rp, const std::vector<int>& r1,
              const std::vector<int>& r2, const std::vector<int>& cp, const std::vector<int>& c1,
              const std::vector<int>& c2);
   };
   void run_kblock(KBatch& kb, int timer_kind);
-  void root_block_jobs(KBatch& kb, cplx* out, int ld, const std::vector<int>& offs);
+  void root_block_jobs(KBatch& kb, const Tree& T, int t, cplx* out, int ld, const std::vector<int>& offs);
+  PointsDev tree_points(const Tree& T) const;
   PointsDev points() const;
   void upload_proxies(const std::vector<double>& px, const std::vector<double>& py,
                       const std::vector<double>& nx, const std::vector<double>& ny,
@@ -164,25 +201,25 @@ class Solver {
   bool own_stream_;
   Uploader up_;
   // geometry
-  int64_t n_ = 0;
+  int64_t n_ = 0;                // nodes of all boundaries
+  std::vector<Tree> trees_;
+  DBuf<MediumDev> media_;        // one per tree
+  int Lmax_ = 0;                 // deepest tree
   std::vector<double> hx_, hy_;  // host copy of the nodes (planning)
   DBuf<double> geo_;             // px, py, nx, ny, w, kappa, each of capacity cap_
   size_t cap_ = 0;
-  symhss_medium med_{};
   symhss_opts opts_{};
-  MediumDev md_{};
   bool two_sided_ = false;
-  int L_ = 0;
-  int root_level_ = 1;      // level whose compressed system is factored densely
-  std::vector<Level> lev_;  // index = level 0..L
-  DBuf<int> rootmap_;       // per box of the root level: positions of its unknowns in the root system
+  int Htop_ = 0;            // highest height holding boxes (max over trees of root_h)
+  std::vector<Level> hev_;  // index = height (0 = leaves)
   DBuf<cplx> scratch_;      // proxy matrices of one level
   DBuf<IdDesc> iddesc_;
   DBuf<int> idint_;
   DBuf<double> idr00_;
-  DBuf<cplx> root_;
+  DBuf<cplx> root_;         // dense top-level systems of all trees
   DBuf<int> rootpiv_, rootinfo_;
-  int root_n_ = 0;
+  size_t rootvec_total_ = 0;  // sum of the trees' root orders
+  DBuf<cplx> rootF_, rootG_;
   DBuf<cplx> vec_;  // staging of b / x for host-pointer solves
   std::vector<TimerPair> timers_;
   std::vector<hipEvent_t> event_pool_;
