@@ -8,6 +8,12 @@ solve, with the boundary geometry and right-hand side already in HBM.
 
 Prints one JSON line.  Workload (default): star r = 1 + 0.3 cos 5t,
 N = 32768 nodes (65536 unknowns), k = 50 / 75, leaf 128, tol 1e-10.
+
+--config 3: a batch of 64 seeded random stars (3-8 arms, amplitude
+U[0.1, 0.3], N log-uniform in [4096, 65536], k_out U[5, 80], k_in = 1.5 k_out)
+solved together in one context: per-level shared launches, autotuned launch
+variants, factorisation and solve replayed as HIP graphs.  Also reports the
+sum of the same boundaries solved one at a time.
 """
 
 from __future__ import annotations
@@ -125,6 +131,102 @@ def _cpu_baseline(wl):
     }
 
 
+def _run_batch(args):
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2609_33216_amd import binding
+
+    wls = workloads.config3_batch(seed=3, count=64)
+    ntot = sum(w.n for w in wls)
+    dev = torch.device("cuda:0")
+    b = torch.zeros(2 * ntot, dtype=torch.complex128, device=dev)
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    s = binding.Solver(0)
+    s.configure(graphs=not args.no_graphs, autotune=True)
+    s.assemble_batch([w.boundary() for w in wls], [(w.k0, w.k1, w.eps0, w.eps1) for w in wls], leaf=128,
+                     tol=1e-10, form=binding.MULLER_SYM)
+    s.rhs_plane_wave_batch_device([w.angle for w in wls], b.data_ptr())
+    print(f"batch: {len(wls)} boundaries, {ntot} nodes; warmup", file=sys.stderr, flush=True)
+    for _ in range(max(args.warmup, 2)):  # tuning, then capture
+        s.compress()
+        s.factor()
+        s.solve_device(b.data_ptr(), x.data_ptr())
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        s.compress()
+        s.factor()
+        s.solve_device(b.data_ptr(), x.data_ptr())
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - t0)
+    st = s.stats()
+    t_batch = sum(per) / len(per)
+    print(f"batch: {1e3 * t_batch:.1f} ms per batch solve; residual", file=sys.stderr, flush=True)
+    y = torch.zeros_like(x)
+    s.lib.symhss_matvec_direct(s.h, binding.ctypes.c_void_p(x.data_ptr()), binding.ctypes.c_void_p(y.data_ptr()),
+                               binding.DEVICE_PTRS)
+    torch.cuda.synchronize()
+    res = []
+    o = 0
+    for w in wls:
+        r = torch.linalg.vector_norm(y[o:o + 2 * w.n] - b[o:o + 2 * w.n]) / torch.linalg.vector_norm(b[o:o + 2 * w.n])
+        res.append(float(r))
+        o += 2 * w.n
+    # the same boundaries one at a time (same options, one warm-up each)
+    t_single = 0.0
+    ent_single = 0
+    if not args.no_single:
+        for i, w in enumerate(wls):
+            s1 = binding.Solver(0)
+            s1.configure(graphs=not args.no_graphs, autotune=True)
+            xw, dxw, ddxw = w.boundary()
+            s1.assemble(xw, dxw, ddxw, w.k0, w.k1, w.eps0, w.eps1, leaf=128, tol=1e-10)
+            b1 = torch.zeros(2 * w.n, dtype=torch.complex128, device=dev)
+            x1 = torch.zeros_like(b1)
+            torch.cuda.synchronize()
+            s1.rhs_plane_wave_device(w.angle, b1.data_ptr())
+            for _ in range(2):
+                s1.compress()
+                s1.factor()
+                s1.solve_device(b1.data_ptr(), x1.data_ptr())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1.compress()
+            s1.factor()
+            s1.solve_device(b1.data_ptr(), x1.data_ptr())
+            torch.cuda.synchronize()
+            t_single += time.perf_counter() - t0
+            s1st = s1.stats()
+            ent_single += s1st["entries_compress"] + s1st["entries_factor"]
+            s1.close()
+    ent = st["entries_compress"] + st["entries_factor"]
+    out = {
+        "metric": "HSS compress+factor s/solve & Gentries/s, sym vs nonsym, at 1e-8 rel err",
+        "value": round(t_batch, 6),
+        "unit": "s/solve (whole 64-boundary batch)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t_batch, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "batch64-stars-seed3", "boundaries": len(wls), "n_nodes_total": ntot,
+                   "n_range": [min(w.n for w in wls), max(w.n for w in wls)], "leaf": 128, "tol": 1e-10,
+                   "form": "symmetric one-sided ID", "graphs": not args.no_graphs, "autotune": True,
+                   "parallelism": "1 GPU"},
+        "boundaries_per_s": round(len(wls) / t_batch, 3),
+        "step_times": [round(v, 6) for v in per],
+        "t_compress": round(st["t_compress"], 6), "t_factor": round(st["t_factor"], 6),
+        "t_solve": round(st["t_solve"], 6),
+        "entries": int(ent),
+        "gentries_per_s_whole_step": round(ent / t_batch / 1e9, 3),
+        "graph_replays": st["graph_replays"], "tuned_buckets": st["tuned_buckets"],
+        "residual_fp64_direct_max": max(res),
+        "unbatched_sum_s": round(t_single, 6) if not args.no_single else None,
+        "speedup_batched_vs_unbatched": round(t_single / t_batch, 3) if not args.no_single else None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,11 +236,17 @@ def main():
     ap.add_argument("--no-base", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-residual", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true", help="batch mode: no HIP-graph replay")
+    ap.add_argument("--no-single", action="store_true", help="batch mode: skip the one-at-a-time sum")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this path has no multi-GPU mode); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == 3:
+        _run_batch(args)
+        return
 
     import numpy as np
     import torch

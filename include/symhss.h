@@ -155,6 +155,24 @@ symhss_status symhss_eval_bessel(symhss_ctx *ctx, int64_t n, const double *z, do
  * pointers unless SYMHSS_DEVICE_PTRS. */
 symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z *y, int32_t flags);
 
+/* Execution options; value in brackets is the default.
+ *  SYMHSS_OPT_GRAPHS      [0] 1: the second time a compressed structure is
+ *       factored, its launch sequence is captured as a HIP graph and every
+ *       later factorisation of the same structure replays it; likewise a
+ *       device-pointer solve repeated with the same vectors and nrhs.  Kernel
+ *       timings in the statistics are not collected for replays.
+ *  SYMHSS_OPT_AUTOTUNE    [0] 1: the first ID and LU launch of each size bucket
+ *       (count, rows, columns) times every launch variant on the real data
+ *       (restored between trials) and keeps the fastest; all variants give
+ *       the same result.
+ *  SYMHSS_OPT_PERSISTENT [-1] ID grid: 0 one workgroup per matrix, 1 a
+ *       persistent grid taking matrices from a work queue, -1 automatic.
+ * EINVAL for an unknown option or value. */
+#define SYMHSS_OPT_GRAPHS 0
+#define SYMHSS_OPT_AUTOTUNE 1
+#define SYMHSS_OPT_PERSISTENT 2
+symhss_status symhss_configure(symhss_ctx *ctx, int32_t option, int64_t value);
+
 /* Statistics of the last assemble/compress/factor/solve. */
 typedef struct {
   int32_t levels;            /* L */
@@ -180,6 +198,8 @@ typedef struct {
   double t_lu_batched, t_lu_multi;  /* seconds, HIP events; t_lu = their sum */
   int32_t n_lu_batched, n_lu_multi;
   double bytes_kblock;       /* 16 bytes per generated entry (compress + factor) */
+  int32_t graph_replays;     /* factorisations and solves served by a HIP graph since assemble */
+  int32_t tuned_buckets;     /* size buckets the autotuner has settled */
 } symhss_stats;
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);

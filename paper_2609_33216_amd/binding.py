@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsymhss.so")
 
 MULLER_SYM, MULLER_BASE, MULLER_SYM_TWOSIDED = 0, 1, 2
 DEVICE_PTRS = 1
+OPT_GRAPHS, OPT_AUTOTUNE, OPT_PERSISTENT = 0, 1, 2
 
 _STATUS = {
     0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ESINGULAR", 6: "ERANK",
@@ -54,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("flops_id", ctypes.c_double), ("flops_lu_batched", ctypes.c_double),
                 ("flops_lu_multi", ctypes.c_double), ("t_lu_batched", ctypes.c_double),
                 ("t_lu_multi", ctypes.c_double), ("n_lu_batched", ctypes.c_int32),
-                ("n_lu_multi", ctypes.c_int32), ("bytes_kblock", ctypes.c_double)]
+                ("n_lu_multi", ctypes.c_int32), ("bytes_kblock", ctypes.c_double),
+                ("graph_replays", ctypes.c_int32), ("tuned_buckets", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_
@@ -71,7 +73,7 @@ EXPORTS = [
     "symhss_create", "symhss_destroy", "symhss_last_error", "symhss_stream", "symhss_assemble",
     "symhss_compress", "symhss_factor", "symhss_solve", "symhss_rhs_plane_wave", "symhss_eval_entries",
     "symhss_eval_bessel", "symhss_matvec_direct", "symhss_get_stats", "symhss_box_query",
-    "symhss_assemble_batch", "symhss_rhs_plane_wave_batch",
+    "symhss_assemble_batch", "symhss_rhs_plane_wave_batch", "symhss_configure",
 ]
 
 _lib = None
@@ -111,6 +113,7 @@ def load(path: str | None = None):
         "symhss_box_query": ([vp, i32, i32, i32, ctypes.POINTER(i64), vp], ctypes.c_int),
         "symhss_assemble_batch": ([vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)], ctypes.c_int),
         "symhss_rhs_plane_wave_batch": ([vp, vp, vp, i32], ctypes.c_int),
+        "symhss_configure": ([vp, i32, i64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -159,6 +162,12 @@ class Solver:
     def _check(self, st: int):
         if st != 0:
             raise SymhssError(st, self.lib.symhss_last_error(self.h).decode())
+
+    def configure(self, graphs: bool | None = None, autotune: bool | None = None, persistent: int | None = None):
+        """Execution options (see symhss_configure)."""
+        for opt, v in ((OPT_GRAPHS, graphs), (OPT_AUTOTUNE, autotune), (OPT_PERSISTENT, persistent)):
+            if v is not None:
+                self._check(self.lib.symhss_configure(self.h, opt, int(v)))
 
     # -- main verbs ------------------------------------------------------
     def assemble(self, x, dx, ddx, k0: float, k1: float, eps0: float = 1.0, eps1: float | None = None,

@@ -145,6 +145,10 @@ symhss_status symhss_matvec_direct(symhss_ctx* ctx, const symhss_z* x, symhss_z*
   });
 }
 
+symhss_status symhss_configure(symhss_ctx* ctx, int32_t option, int64_t value) {
+  return guarded(ctx, [&](symhss::Solver& s) { s.configure(option, value); });
+}
+
 symhss_status symhss_get_stats(const symhss_ctx* ctx, symhss_stats* out) {
   if (!ctx || !ctx->s || !out) return SYMHSS_EINVAL;
   *out = ctx->s->stats();

@@ -11,16 +11,20 @@
 // R12 overwrites R12, so that M[:, P[k:]] ~= M[:, P[:k]] T; a pass that may
 // be resumed leaves R12 in place.
 //
-// One workgroup (4 wavefronts) per matrix.  The Householder vector of the
-// current step is staged in LDS; every wavefront then takes a stride of the
-// trailing columns, forms v^H a_c with a wavefront reduction, applies the
-// reflector and recomputes the column's trailing norm in the same pass.
+// One workgroup per matrix.  The Householder vector of the current step is
+// staged in LDS; every wavefront then takes groups of trailing columns,
+// forms v^H a_c with wavefront reductions, applies the reflector and
+// recomputes the columns' trailing norms in the same pass.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace symhss {
 
 
-constexpr int kRegRows = 8;  // register-cached column segment: up to 512 rows
+__global__ void k_zero_i32(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -28,14 +32,106 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-template <int kIdThreads>
-__global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ descs, double tol, int want_T) {
-  extern __shared__ double lds[];
-  const IdDesc D = descs[blockIdx.x];
+// Apply the step's reflector H = I - tau v v^H to CB consecutive columns
+// c0 .. c0+CB-1 (those < n) over rows j..m-1 and recompute their norms below
+// row j.  The column segments (R*64 rows per column) are loaded into
+// registers together, so one wavefront keeps CB*R loads in flight.
+template <int R, int CB>
+__device__ inline void reflect_columns(const IdDesc& D, int j, int c0, const cplx* __restrict__ vj, double tau,
+                                       double* vn, int lane) {
+  const int m = D.m, n = D.n;
+  const long ld = D.ld;
+  const int rows = m - j;
+  cplx a[CB][R];
+  cplx w[CB];
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
+    const int c = c0 + b;
+    const cplx* col = D.A + ld * (c < n ? c : 0) + j;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = lane + 64 * q;
+      a[b][q] = (c < n && i < rows) ? col[i] : mk(0, 0);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
+    w[b] = mk(0, 0);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = lane + 64 * q;
+      if (i < rows) fma_conj_acc(w[b], vj[i], a[b][q]);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      w[b].re += __shfl_xor(w[b].re, off, 64);
+      w[b].im += __shfl_xor(w[b].im, off, 64);
+    }
+  }
+  double s[CB];
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
+    const int c = c0 + b;
+    const cplx tw = tau * w[b];
+    cplx* col = D.A + ld * (c < n ? c : 0) + j;
+    s[b] = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = lane + 64 * q;
+      if (c < n && i < rows) {
+        const cplx vi = vj[i];
+        a[b][q].re -= vi.re * tw.re - vi.im * tw.im;
+        a[b][q].im -= vi.re * tw.im + vi.im * tw.re;
+        col[i] = a[b][q];
+        if (i > 0) s[b] += abs2(a[b][q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int b = 0; b < CB; ++b) s[b] += __shfl_xor(s[b], off, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+      if (c0 + b < n) vn[c0 + b] = s[b];
+  }
+}
+
+// One column, any number of rows (streamed from global memory).
+__device__ inline void reflect_column_long(const IdDesc& D, int j, int c, const cplx* __restrict__ vj, double tau,
+                                           double* vn, int lane) {
+  const int rows = D.m - j;
+  cplx* col = D.A + (long)D.ld * c + j;
+  cplx w = mk(0, 0);
+  for (int i = lane; i < rows; i += 64) fma_conj_acc(w, vj[i], col[i]);
+  w.re = wave_sum(w.re);
+  w.im = wave_sum(w.im);
+  const cplx tw = tau * w;
+  double s = 0.0;
+  for (int i = lane; i < rows; i += 64) {
+    cplx a = col[i];
+    const cplx vi = vj[i];
+    a.re -= vi.re * tw.re - vi.im * tw.im;
+    a.im -= vi.re * tw.im + vi.im * tw.re;
+    col[i] = a;
+    if (i > 0) s += abs2(a);
+  }
+  s = wave_sum(s);
+  if (lane == 0) vn[c] = s;
+}
+
+// The ID of one matrix by one workgroup of NT threads.
+template <int NT, int R, int CB>
+__device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
   const int m = D.m, n = D.n;
   const long ld = D.ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int nwaves = kIdThreads / 64;
+  constexpr int nwaves = NT / 64;
   // LDS: vn[n] doubles, v[m] complex, reduction scratch
   double* vn = lds;
   cplx* v = reinterpret_cast<cplx*>(lds + n);
@@ -48,7 +144,7 @@ __global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ 
   const int kmax = m < n ? m : n;
   int j0 = (D.target >= 0) ? *D.rank : 0;
   if (j0 == 0) {
-    for (int c = tid; c < n; c += kIdThreads) D.perm[c] = c;
+    for (int c = tid; c < n; c += NT) D.perm[c] = c;
   }
   __syncthreads();
   // trailing norms over rows j0..m-1
@@ -68,7 +164,7 @@ __global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ 
     // pivot: argmax vn[c], c >= j, lowest index on ties
     double best = -1.0;
     int bi = n;
-    for (int c = j + tid; c < n; c += kIdThreads) {
+    for (int c = j + tid; c < n; c += NT) {
       const double x = vn[c];
       if (x > best) { best = x; bi = c; }
     }
@@ -105,7 +201,7 @@ __global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ 
     if (p != j) {
       cplx* cj = D.A + ld * j;
       cplx* cp = D.A + ld * p;
-      for (int i = tid; i < m; i += kIdThreads) {
+      for (int i = tid; i < m; i += NT) {
         const cplx t = cj[i];
         cj[i] = cp[i];
         cp[i] = t;
@@ -156,56 +252,12 @@ __global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ 
     }
     __syncthreads();
     const double tau = s_tau;
-    // apply to trailing columns, recompute their norms below row j; a column
-    // segment of up to kRegRows * 64 rows is read once into registers
+    // apply to the trailing columns, CB at a time per wavefront
     const int rows = m - j;
-    for (int c = j + 1 + wave; c < n; c += nwaves) {
-      cplx* col = D.A + ld * c + j;
-      const cplx* vj = v + j;
-      if (rows <= kRegRows * 64) {
-        cplx a[kRegRows];
-        cplx w = mk(0, 0);
-#pragma unroll
-        for (int q = 0; q < kRegRows; ++q) {
-          const int i = lane + 64 * q;
-          a[q] = i < rows ? col[i] : mk(0, 0);
-          if (i < rows) fma_conj_acc(w, vj[i], a[q]);
-        }
-        w.re = wave_sum(w.re);
-        w.im = wave_sum(w.im);
-        const cplx tw = tau * w;
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < kRegRows; ++q) {
-          const int i = lane + 64 * q;
-          if (i < rows) {
-            const cplx vi = vj[i];
-            a[q].re -= vi.re * tw.re - vi.im * tw.im;
-            a[q].im -= vi.re * tw.im + vi.im * tw.re;
-            col[i] = a[q];
-            if (i > 0) s += abs2(a[q]);
-          }
-        }
-        s = wave_sum(s);
-        if (lane == 0) vn[c] = s;
-      } else {
-        cplx w = mk(0, 0);
-        for (int i = lane; i < rows; i += 64) fma_conj_acc(w, vj[i], col[i]);
-        w.re = wave_sum(w.re);
-        w.im = wave_sum(w.im);
-        const cplx tw = tau * w;
-        double s = 0.0;
-        for (int i = lane; i < rows; i += 64) {
-          cplx a = col[i];
-          const cplx vi = vj[i];
-          a.re -= vi.re * tw.re - vi.im * tw.im;
-          a.im -= vi.re * tw.im + vi.im * tw.re;
-          col[i] = a;
-          if (i > 0) s += abs2(a);
-        }
-        s = wave_sum(s);
-        if (lane == 0) vn[c] = s;
-      }
+    if (rows <= R * 64) {
+      for (int c0 = j + 1 + CB * wave; c0 < n; c0 += CB * nwaves) reflect_columns<R, CB>(D, j, c0, v + j, tau, vn, lane);
+    } else {
+      for (int c = j + 1 + wave; c < n; c += nwaves) reflect_column_long(D, j, c, v + j, tau, vn, lane);
     }
     __syncthreads();
   }
@@ -214,7 +266,7 @@ __global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ 
   __syncthreads();
   if (want_T) {
     // T = R11^{-1} R12 in place, one column per thread
-    for (int c = k + tid; c < n; c += kIdThreads) {
+    for (int c = k + tid; c < n; c += NT) {
       cplx* col = D.A + ld * c;
       for (int i = k - 1; i >= 0; --i) {
         cplx s = col[i];
@@ -227,6 +279,32 @@ __global__ __launch_bounds__(kIdThreads) void k_cpqr(const IdDesc* __restrict__ 
         col[i] = cdiv(s, D.A[i + ld * i]);
       }
     }
+  }
+}
+
+// One workgroup per matrix (queue == nullptr), or a persistent grid whose
+// workgroups take matrices from a work queue: *queue counts the matrices
+// handed out and must be zero at launch.  Every workgroup leaves the loop
+// once the counter passes count.
+template <int NT, int R, int CB>
+__global__ __launch_bounds__(NT) void k_cpqr(const IdDesc* __restrict__ descs, int count, double tol, int want_T,
+                                             int* queue) {
+  extern __shared__ double lds[];
+  if (queue == nullptr) {
+    const IdDesc D = descs[blockIdx.x];
+    cpqr_one<NT, R, CB>(D, tol, want_T, lds);
+    return;
+  }
+  __shared__ int s_next;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int d = s_next;
+    __syncthreads();
+    if (d >= count) break;
+    const IdDesc D = descs[d];
+    cpqr_one<NT, R, CB>(D, tol, want_T, lds);
+    __syncthreads();
   }
 }
 
@@ -267,17 +345,53 @@ size_t cpqr_lds_bytes(int mmax, int nmax) {
   return sizeof(double) * (size_t)nmax + sizeof(cplx) * (size_t)mmax + 16 * (sizeof(double) + sizeof(int)) + 64;
 }
 
-void launch_cpqr(hipStream_t st, const IdDesc* descs, int count, int mmax, int nmax, double tol, int want_T) {
+// Variants: 256 threads (4 wavefronts, several workgroups per CU; CB = 4
+// columns per wavefront) or 1024 threads (16 wavefronts for few, large
+// matrices; CB = 2, or 1 with 8 register rows, to stay within 128
+// registers); R = 4 or 8 register rows
+// per lane by the tallest matrix.  persistent: queue-driven grid sized to the
+// resident workgroups.
+template <int NT, int R, int CB>
+static void launch_cpqr_t(hipStream_t st, const IdDesc* descs, int count, size_t lds, double tol, int want_T,
+                          int* queue) {
+  if (!queue) {
+    hipLaunchKernelGGL((k_cpqr<NT, R, CB>), dim3(count), dim3(NT), lds, st, descs, count, tol, want_T, nullptr);
+    return;
+  }
+  int dev = 0, ncu = 0, per = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cpqr<NT, R, CB>, NT, lds));
+  const int grid = std::max(1, std::min(count, ncu * std::max(per, 1)));
+  hipLaunchKernelGGL((k_cpqr<NT, R, CB>), dim3(grid), dim3(NT), lds, st, descs, count, tol, want_T, queue);
+}
+
+void launch_cpqr(hipStream_t st, const IdDesc* descs, int count, int mmax, int nmax, double tol, int want_T,
+                 const CpqrVariant& var, int* queue) {
   if (count <= 0) return;
   const size_t lds = cpqr_lds_bytes(mmax, nmax);
   if (lds > 160 * 1024) throw std::runtime_error("proxy matrix too large for the ID kernel's LDS staging");
-  // many matrices: 4 wavefronts each, several workgroups per CU; few (large)
-  // matrices: 16 wavefronts per workgroup to keep the CU's memory pipe busy
-  if (count >= 128)
-    hipLaunchKernelGGL(k_cpqr<256>, dim3(count), dim3(256), lds, st, descs, tol, want_T);
-  else
-    hipLaunchKernelGGL(k_cpqr<1024>, dim3(count), dim3(1024), lds, st, descs, tol, want_T);
+  int* q = var.persistent ? queue : nullptr;
+  if (var.persistent) {
+    if (!queue) throw std::invalid_argument("persistent ID launch without a queue counter");
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, queue, 1);
+  }
+  const bool tall = mmax > 256;
+  if (var.threads == 1024) {
+    if (tall) launch_cpqr_t<1024, 8, 1>(st, descs, count, lds, tol, want_T, q);
+    else launch_cpqr_t<1024, 4, 2>(st, descs, count, lds, tol, want_T, q);
+  } else {
+    if (tall) launch_cpqr_t<256, 8, 4>(st, descs, count, lds, tol, want_T, q);
+    else launch_cpqr_t<256, 4, 4>(st, descs, count, lds, tol, want_T, q);
+  }
   HIPCHK(hipGetLastError());
+}
+
+CpqrVariant cpqr_default_variant(int count) {
+  CpqrVariant v;
+  v.threads = count >= 128 ? 256 : 1024;
+  v.persistent = 0;
+  return v;
 }
 
 void launch_build_interp(hipStream_t st, const InterpDesc* descs, int count, int nmax) {

@@ -86,9 +86,19 @@ void launch_matvec_direct(hipStream_t st, const PointsDev& P, const MediumDev& m
 
 // interpolative decomposition (cpqr.hip)
 size_t cpqr_lds_bytes(int mmax, int nmax);
-void launch_cpqr(hipStream_t st, const IdDesc* descs, int count, int mmax, int nmax, double tol, int want_T);
+struct CpqrVariant {
+  int threads = 256;   // 256 or 1024 per workgroup
+  int persistent = 0;  // 1: work-queue grid (needs a device counter)
+};
+CpqrVariant cpqr_default_variant(int count);
+// queue: one device int, used (and zeroed first) by persistent variants
+void launch_cpqr(hipStream_t st, const IdDesc* descs, int count, int mmax, int nmax, double tol, int want_T,
+                 const CpqrVariant& var, int* queue);
 void launch_build_interp(hipStream_t st, const InterpDesc* descs, int count, int nmax);
 void launch_equalise_ranks(hipStream_t st, int npairs, const int* ia, const int* ib, IdDesc* descs);
+
+// one-thread-per-element int zeroing (graph-safe, no memset node)
+__global__ void k_zero_i32(int* p, int n);
 
 // batched dense algebra (dense.hip)
 void launch_lu_fused(hipStream_t st, const LuDesc* d, int count);

@@ -49,14 +49,20 @@ struct DBuf {
 // driver calls only after the stream has drained.
 class Uploader {
  public:
-  explicit Uploader(hipStream_t st) : st_(st) {}
+  Uploader() = default;
+  Uploader(const Uploader&) = delete;
+  Uploader& operator=(const Uploader&) = delete;
   ~Uploader();
+  void set_stream(hipStream_t st) { st_ = st; }
   template <class T>
   T* put(const std::vector<T>& v) {
     return static_cast<T*>(put_bytes(v.data(), v.size() * sizeof(T)));
   }
   void* put_bytes(const void* src, size_t bytes);
   void reset();
+  size_t used() const;
+  // one chunk with at least `bytes` free, so that later puts allocate nothing
+  void reserve(size_t bytes);
 
  private:
   struct Chunk {
@@ -64,8 +70,9 @@ class Uploader {
     char* h;
     size_t cap, used;
   };
-  hipStream_t st_;
+  hipStream_t st_ = nullptr;
   std::vector<Chunk> chunks_;
+  Chunk& new_chunk(size_t cap);
 };
 
 // Geometry of one box of a boundary's full binary tree.
@@ -155,7 +162,12 @@ class Solver {
   void eval_bessel(int64_t n, const double* z, double* out);
   void matvec_direct(const symhss_z* x, symhss_z* y, int flags);
   void box_query(int level, int box, int what, int64_t* count, void* out);
-  symhss_stats stats() const { return stats_; }
+  void configure(int what, int64_t value);
+  symhss_stats stats() const {
+    symhss_stats s = stats_;
+    s.tuned_buckets = (int32_t)tuned_.size();
+    return s;
+  }
   hipStream_t stream() const { return st_; }
 
   int stage = 0;  // 0 none, 1 assembled, 2 compressed, 3 factored
@@ -173,8 +185,16 @@ class Solver {
   // compress pieces
   void compress_level(int h);
   // factor pieces
+  void factor_layout();
   void factor_level(int h);
   void factor_root();
+  void factor_enqueue();
+  uint64_t plan_signature() const;
+  // launches with a choice of variant (autotuned per size bucket when enabled)
+  void run_cpqr(const IdDesc* d, int count, int mmax, int nmax, int want_T, cplx* data, size_t data_elems);
+  void run_lu(const LuDesc* d, int count, int nmax, int ncolmax, int nrhsmax, cplx* data, size_t data_elems,
+              int* info, int ninfo, double flops);
+  void solve_enqueue(const cplx* db, cplx* dx, int nrhs);
   // kernel-block launches
   struct KBatch {
     std::vector<KJob> jobs;
@@ -199,7 +219,9 @@ class Solver {
   int device_;  // HIP device the context was created on
   hipStream_t st_;
   bool own_stream_;
-  Uploader up_;
+  Uploader up_;          // eager work: reset after every phase
+  Uploader fgup_, sgup_;  // descriptors read by the captured factor / solve graphs
+  Uploader* upl_ = &up_;
   // geometry
   int64_t n_ = 0;                // nodes of all boundaries
   std::vector<Tree> trees_;
@@ -221,6 +243,24 @@ class Solver {
   size_t rootvec_total_ = 0;  // sum of the trees' root orders
   DBuf<cplx> rootF_, rootG_;
   DBuf<cplx> vec_;  // staging of b / x for host-pointer solves
+  // execution options (symhss_configure)
+  int use_graphs_ = 0, autotune_ = 0, persistent_ = -1;
+  bool capturing_ = false;
+  uint64_t plan_sig_ = 0;     // structure produced by the last compress
+  uint64_t assemble_gen_ = 0;
+  uint64_t fsig_ = 0;         // structure the factor graph was captured for
+  int fseen_ = 0;             // factors run with that structure
+  hipGraphExec_t fgraph_ = nullptr;
+  uint64_t ssig_ = 0;
+  int sseen_ = 0;
+  hipGraphExec_t sgraph_ = nullptr;
+  size_t last_factor_upload_ = 0, last_solve_upload_ = 0;  // descriptor bytes of the last eager runs
+  void drop_graphs();
+  // autotuner: size bucket -> chosen variant
+  std::vector<std::pair<uint64_t, int>> tuned_;
+  int tuned_choice(uint64_t key) const;
+  DBuf<cplx> tune_backup_;
+  DBuf<int> queue_;
   std::vector<TimerPair> timers_;
   std::vector<hipEvent_t> event_pool_;
   symhss_stats stats_{};
