@@ -171,7 +171,63 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
 #define SYMHSS_OPT_GRAPHS 0
 #define SYMHSS_OPT_AUTOTUNE 1
 #define SYMHSS_OPT_PERSISTENT 2
+#define SYMHSS_OPT_PREDICTOR 3
+#define SYMHSS_OPT_PROXY_MARGIN 4
 symhss_status symhss_configure(symhss_ctx *ctx, int32_t option, int64_t value);
+
+/* Rank predictor (sizes fixed before the factorisation runs, Section 4.3):
+ * a 6 -> 64 -> 64 -> 64 -> 1 ReLU network in FP32 predicting log(rank) of a
+ * box, the larger of its two halves' ranks, from its features
+ *   (k_out d, k_in d, mean |kappa| d, max |kappa| d, level, log10 tol),
+ * d = box diameter (twice the largest distance of its nodes from the
+ * bounding-box midpoint), kappa = curvature at its nodes, level = the box's
+ * level in its boundary's tree.  Features are float, 6 per sample, row-major.
+ *
+ * Weights: SYMHSS_PREDICTOR_WEIGHTS floats = the 8833 network parameters
+ * (W1 64x6 row-major, b1, W2 64x64, b2, W3 64x64, b3, W4 1x64, b4) followed
+ * by the 6 feature means and 6 feature scales used to normalise inputs.
+ *
+ * With SYMHSS_OPT_PREDICTOR = 1 (weights loaded or trained), compress sizes
+ * each box's proxy circle from its predicted rank k^:
+ *   n_p = min(rule, roundup16(max(32, ceil(k^) + margin))),
+ * margin = SYMHSS_OPT_PROXY_MARGIN [16], rule = the count used without the
+ * predictor; a box whose measured rank exceeds k^ is compressed again with
+ * the rule's count (the adaptive column-pivoted QR stays the judge). */
+#define SYMHSS_PREDICTOR_WEIGHTS 8845
+typedef struct {
+  int32_t epochs;  /* passes over the samples (>= 1) */
+  int32_t batch;   /* mini-batch size (>= 1) */
+  float lr;        /* Adam step size (> 0); beta1 0.9, beta2 0.999, eps 1e-8 */
+  float alpha;     /* weight of under-predicted samples in the loss (>= 1) */
+  uint64_t seed;   /* initialisation and shuffling */
+} symhss_train_params;
+
+/* Train on the GPU from n samples (feat: n x 6, rank: n values >= 1); the
+ * loss is (1/B) sum c_s (yhat_s - log rank_s)^2 per mini-batch of B, with
+ * c_s = alpha for under-predictions and 1 otherwise.  history (may be NULL):
+ * epochs floats, the mean mini-batch loss of each epoch.  The trained
+ * weights stay in the context. */
+symhss_status symhss_predictor_train(symhss_ctx *ctx, const float *feat, const float *rank, int64_t n,
+                                     const symhss_train_params *hp, float *history);
+/* Load / read SYMHSS_PREDICTOR_WEIGHTS floats (host memory). */
+symhss_status symhss_predictor_load(symhss_ctx *ctx, const float *weights, int64_t count);
+symhss_status symhss_predictor_get(symhss_ctx *ctx, float *weights, int64_t count);
+/* rank_out[s] = exp(network(feat[s])) for n samples (host memory). */
+symhss_status symhss_predictor_predict(symhss_ctx *ctx, const float *feat, int64_t n, float *rank_out);
+/* Training data after compress: for every compressed box (heights from the
+ * leaves up, boundaries in order within a height) its 6 predictor features
+ * (feat, count x 6), its measured rank, the larger of its halves' ranks
+ * (rank), and info (count x 6 int32: boundary, level in its boundary's tree,
+ * first node, one past the last node, proxy count used, predicted rank or 0).
+ * Any output may be NULL; with all NULL only *count is set, otherwise *count
+ * must hold the capacity (EINVAL if too small) and receives the count. */
+symhss_status symhss_box_table(symhss_ctx *ctx, int64_t *count, float *feat, int32_t *rank, int32_t *info);
+
+/* Verification: loss and its gradient (8833 floats) over all n samples as one
+ * batch, for the given weights (SYMHSS_PREDICTOR_WEIGHTS floats); replaces the
+ * context's weights with them. */
+symhss_status symhss_predictor_grad(symhss_ctx *ctx, const float *weights, const float *feat, const float *rank,
+                                    int64_t n, float alpha, float *grad, float *loss);
 
 /* Statistics of the last assemble/compress/factor/solve. */
 typedef struct {
@@ -200,6 +256,11 @@ typedef struct {
   double bytes_kblock;       /* 16 bytes per generated entry (compress + factor) */
   int32_t graph_replays;     /* factorisations and solves served by a HIP graph since assemble */
   int32_t tuned_buckets;     /* size buckets the autotuner has settled */
+  /* predictor-sized compression (last compress) */
+  int32_t pred_boxes;        /* boxes whose proxy count came from the predictor */
+  int32_t pred_fallbacks;    /* of those, compressed again with the rule's count */
+  int64_t proxy_rows;        /* proxy-matrix rows generated (all passes) */
+  int64_t proxy_rows_rule;   /* rows the rule's counts would have generated */
 } symhss_stats;
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);

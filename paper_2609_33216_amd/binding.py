@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsymhss.so")
 
 MULLER_SYM, MULLER_BASE, MULLER_SYM_TWOSIDED = 0, 1, 2
 DEVICE_PTRS = 1
-OPT_GRAPHS, OPT_AUTOTUNE, OPT_PERSISTENT = 0, 1, 2
+OPT_GRAPHS, OPT_AUTOTUNE, OPT_PERSISTENT, OPT_PREDICTOR, OPT_PROXY_MARGIN = 0, 1, 2, 3, 4
 
 _STATUS = {
     0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ESINGULAR", 6: "ERANK",
@@ -56,7 +56,9 @@ class Stats(ctypes.Structure):
                 ("flops_lu_multi", ctypes.c_double), ("t_lu_batched", ctypes.c_double),
                 ("t_lu_multi", ctypes.c_double), ("n_lu_batched", ctypes.c_int32),
                 ("n_lu_multi", ctypes.c_int32), ("bytes_kblock", ctypes.c_double),
-                ("graph_replays", ctypes.c_int32), ("tuned_buckets", ctypes.c_int32)]
+                ("graph_replays", ctypes.c_int32), ("tuned_buckets", ctypes.c_int32),
+                ("pred_boxes", ctypes.c_int32), ("pred_fallbacks", ctypes.c_int32),
+                ("proxy_rows", ctypes.c_int64), ("proxy_rows_rule", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_
@@ -74,7 +76,17 @@ EXPORTS = [
     "symhss_compress", "symhss_factor", "symhss_solve", "symhss_rhs_plane_wave", "symhss_eval_entries",
     "symhss_eval_bessel", "symhss_matvec_direct", "symhss_get_stats", "symhss_box_query",
     "symhss_assemble_batch", "symhss_rhs_plane_wave_batch", "symhss_configure",
+    "symhss_predictor_train", "symhss_predictor_load", "symhss_predictor_get", "symhss_predictor_predict",
+    "symhss_predictor_grad", "symhss_box_table",
 ]
+
+PREDICTOR_WEIGHTS = 8845
+N_FEATURES = 6
+
+
+class TrainParams(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("alpha", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 _lib = None
 
@@ -114,6 +126,12 @@ def load(path: str | None = None):
         "symhss_assemble_batch": ([vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)], ctypes.c_int),
         "symhss_rhs_plane_wave_batch": ([vp, vp, vp, i32], ctypes.c_int),
         "symhss_configure": ([vp, i32, i64], ctypes.c_int),
+        "symhss_predictor_train": ([vp, vp, vp, i64, ctypes.POINTER(TrainParams), vp], ctypes.c_int),
+        "symhss_predictor_load": ([vp, vp, i64], ctypes.c_int),
+        "symhss_predictor_get": ([vp, vp, i64], ctypes.c_int),
+        "symhss_predictor_predict": ([vp, vp, i64, vp], ctypes.c_int),
+        "symhss_predictor_grad": ([vp, vp, vp, vp, i64, ctypes.c_float, vp, vp], ctypes.c_int),
+        "symhss_box_table": ([vp, ctypes.POINTER(i64), vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -163,11 +181,62 @@ class Solver:
         if st != 0:
             raise SymhssError(st, self.lib.symhss_last_error(self.h).decode())
 
-    def configure(self, graphs: bool | None = None, autotune: bool | None = None, persistent: int | None = None):
+    def configure(self, graphs: bool | None = None, autotune: bool | None = None, persistent: int | None = None,
+                  predictor: bool | None = None, proxy_margin: int | None = None):
         """Execution options (see symhss_configure)."""
-        for opt, v in ((OPT_GRAPHS, graphs), (OPT_AUTOTUNE, autotune), (OPT_PERSISTENT, persistent)):
+        for opt, v in ((OPT_GRAPHS, graphs), (OPT_AUTOTUNE, autotune), (OPT_PERSISTENT, persistent),
+                       (OPT_PREDICTOR, predictor), (OPT_PROXY_MARGIN, proxy_margin)):
             if v is not None:
                 self._check(self.lib.symhss_configure(self.h, opt, int(v)))
+
+    # -- rank predictor --------------------------------------------------
+    def predictor_train(self, feat, rank, epochs=200, batch=1024, lr=2e-3, alpha=4.0, seed=0):
+        feat = np.ascontiguousarray(feat, dtype=np.float32)
+        rank = np.ascontiguousarray(rank, dtype=np.float32)
+        if feat.ndim != 2 or feat.shape[1] != N_FEATURES or rank.shape != (feat.shape[0],):
+            raise ValueError("feat must be (n, 6) and rank (n,)")
+        hist = np.zeros(epochs, dtype=np.float32)
+        hp = TrainParams(epochs, batch, lr, alpha, seed)
+        self._check(self.lib.symhss_predictor_train(self.h, _ptr(feat), _ptr(rank), feat.shape[0], ctypes.byref(hp),
+                                                    _ptr(hist)))
+        return hist
+
+    def predictor_load(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self.lib.symhss_predictor_load(self.h, _ptr(w), w.size))
+
+    def predictor_get(self):
+        w = np.zeros(PREDICTOR_WEIGHTS, dtype=np.float32)
+        self._check(self.lib.symhss_predictor_get(self.h, _ptr(w), w.size))
+        return w
+
+    def predictor_predict(self, feat):
+        feat = np.ascontiguousarray(feat, dtype=np.float32)
+        out = np.zeros(feat.shape[0], dtype=np.float32)
+        self._check(self.lib.symhss_predictor_predict(self.h, _ptr(feat), feat.shape[0], _ptr(out)))
+        return out
+
+    def predictor_grad(self, w, feat, rank, alpha):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        feat = np.ascontiguousarray(feat, dtype=np.float32)
+        rank = np.ascontiguousarray(rank, dtype=np.float32)
+        g = np.zeros(PREDICTOR_WEIGHTS - 2 * N_FEATURES, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        self._check(self.lib.symhss_predictor_grad(self.h, _ptr(w), _ptr(feat), _ptr(rank), feat.shape[0],
+                                                   ctypes.c_float(alpha), _ptr(g), _ptr(loss)))
+        return float(loss[0]), g
+
+    def box_table(self):
+        """(features (n, 6) float32, measured ranks (n,), info (n, 6)) of every compressed box."""
+        cnt = ctypes.c_int64(0)
+        self._check(self.lib.symhss_box_table(self.h, ctypes.byref(cnt), None, None, None))
+        n = cnt.value
+        feat = np.zeros((n, N_FEATURES), dtype=np.float32)
+        rank = np.zeros(n, dtype=np.int32)
+        info = np.zeros((n, 6), dtype=np.int32)
+        if n:
+            self._check(self.lib.symhss_box_table(self.h, ctypes.byref(cnt), _ptr(feat), _ptr(rank), _ptr(info)))
+        return feat, rank, info
 
     # -- main verbs ------------------------------------------------------
     def assemble(self, x, dx, ddx, k0: float, k1: float, eps0: float = 1.0, eps1: float | None = None,

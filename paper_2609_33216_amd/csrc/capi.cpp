@@ -1,6 +1,7 @@
 // C-ABI of the solver (include/symhss.h): argument checks, the stage
 // machine and the mapping of C++ exceptions to status codes.  No exception
 // crosses this boundary.
+#include <cmath>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -147,6 +148,53 @@ symhss_status symhss_matvec_direct(symhss_ctx* ctx, const symhss_z* x, symhss_z*
 
 symhss_status symhss_configure(symhss_ctx* ctx, int32_t option, int64_t value) {
   return guarded(ctx, [&](symhss::Solver& s) { s.configure(option, value); });
+}
+
+symhss_status symhss_predictor_train(symhss_ctx* ctx, const float* feat, const float* rank, int64_t n,
+                                     const symhss_train_params* hp, float* history) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    if (!feat || !rank || !hp) throw std::invalid_argument("null argument");
+    s.predictor().train(s.stream(), feat, rank, n, *hp, history);
+  });
+}
+
+symhss_status symhss_predictor_load(symhss_ctx* ctx, const float* weights, int64_t count) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    if (!weights || count != SYMHSS_PREDICTOR_WEIGHTS) throw std::invalid_argument("need SYMHSS_PREDICTOR_WEIGHTS floats");
+    for (int64_t i = 0; i < count; ++i)
+      if (!std::isfinite(weights[i])) throw std::invalid_argument("non-finite weight");
+    s.predictor().set_params(weights, s.stream());
+  });
+}
+
+symhss_status symhss_predictor_get(symhss_ctx* ctx, float* weights, int64_t count) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    if (!weights || count != SYMHSS_PREDICTOR_WEIGHTS) throw std::invalid_argument("need SYMHSS_PREDICTOR_WEIGHTS floats");
+    s.predictor().get_params(weights, s.stream());
+  });
+}
+
+symhss_status symhss_predictor_predict(symhss_ctx* ctx, const float* feat, int64_t n, float* rank_out) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    if (n < 0 || (n && (!feat || !rank_out))) throw std::invalid_argument("bad arguments");
+    s.predictor().predict(s.stream(), feat, n, rank_out);
+  });
+}
+
+symhss_status symhss_predictor_grad(symhss_ctx* ctx, const float* weights, const float* feat, const float* rank,
+                                    int64_t n, float alpha, float* grad, float* loss) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    if (!weights || !feat || !rank || !grad || !loss) throw std::invalid_argument("null argument");
+    if (!(alpha >= 1.0f)) throw std::invalid_argument("alpha must be >= 1");
+    s.predictor().gradient(s.stream(), weights, feat, rank, n, alpha, grad, loss);
+  });
+}
+
+symhss_status symhss_box_table(symhss_ctx* ctx, int64_t* count, float* feat, int32_t* rank, int32_t* info) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    if (!count) throw std::invalid_argument("null count");
+    s.box_table(count, feat, rank, info);
+  });
 }
 
 symhss_status symhss_get_stats(const symhss_ctx* ctx, symhss_stats* out) {

@@ -8,6 +8,7 @@
 
 #include "bessel.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "../../include/symhss.h"
 
 namespace symhss {
@@ -79,6 +80,7 @@ class Uploader {
 struct BoxGeom {
   int lo = 0, hi = 0;  // node range (global node ids)
   double cx = 0, cy = 0, rad = 0;
+  double kmean = 0, kmax = 0;  // mean and largest |curvature| over its nodes
 };
 
 struct Box {
@@ -86,6 +88,7 @@ struct Box {
   double cx = 0, cy = 0, rad = 0;
   int tree = 0;               // boundary of a batch
   int li = 0;                 // index among its tree's boxes at this height
+  double kmean = 0, kmax = 0; // |curvature| statistics of its nodes
   std::vector<int> rows[2];   // active row node ids: first / second equation
   std::vector<int> cols[2];   // active column node ids: q / u unknowns
   std::vector<int> rsk[2];    // row skeleton: local indices into rows[h]
@@ -94,6 +97,8 @@ struct Box {
   std::vector<int> nearc[2];  // near-field columns (node ids) for M_L
   double Rp = 0;
   int np = 0;
+  int np_rule = 0;            // proxy count of the rule (without the predictor)
+  int khat = 0;               // predicted rank (0: no prediction)
   int sr() const { return (int)(rows[0].size() + rows[1].size()); }
   int sc() const { return (int)(cols[0].size() + cols[1].size()); }
   int kc() const { return (int)(csk[0].size() + csk[1].size()); }
@@ -163,6 +168,8 @@ class Solver {
   void matvec_direct(const symhss_z* x, symhss_z* y, int flags);
   void box_query(int level, int box, int what, int64_t* count, void* out);
   void configure(int what, int64_t value);
+  Mlp& predictor() { return mlp_; }
+  void box_table(int64_t* count, float* feat, int32_t* rank, int32_t* info) const;
   symhss_stats stats() const {
     symhss_stats s = stats_;
     s.tuned_buckets = (int32_t)tuned_.size();
@@ -184,6 +191,21 @@ class Solver {
   }
   // compress pieces
   void compress_level(int h);
+  // one generation + ID pass over some boxes of a height
+  struct IdPass {
+    DBuf<cplx> scratch;     // the boxes' proxy matrices, factored in place
+    DBuf<int> idint;        // pivots, then ranks
+    DBuf<double> r00;
+    std::vector<IdDesc> ds;
+    std::vector<size_t> permoff;
+    std::vector<int> hint;  // host copy of idint
+    std::vector<int> boxes; // box indices of the pass
+    size_t ptot = 0;
+    int per = 2;
+  };
+  IdPass pass_[2];  // [0] all boxes, [1] predictor fallbacks
+  void proxy_ids(int h, const std::vector<int>& which, IdPass& P);
+  void box_features_of(int h, const Box& B, float* f) const;
   // factor pieces
   void factor_layout();
   void factor_level(int h);
@@ -228,16 +250,15 @@ class Solver {
   DBuf<MediumDev> media_;        // one per tree
   int Lmax_ = 0;                 // deepest tree
   std::vector<double> hx_, hy_;  // host copy of the nodes (planning)
+  std::vector<double> hk_;       // curvature at the nodes (predictor features)
+  Mlp mlp_;
+  int use_predictor_ = 0, proxy_margin_ = 16;
   DBuf<double> geo_;             // px, py, nx, ny, w, kappa, each of capacity cap_
   size_t cap_ = 0;
   symhss_opts opts_{};
   bool two_sided_ = false;
   int Htop_ = 0;            // highest height holding boxes (max over trees of root_h)
   std::vector<Level> hev_;  // index = height (0 = leaves)
-  DBuf<cplx> scratch_;      // proxy matrices of one level
-  DBuf<IdDesc> iddesc_;
-  DBuf<int> idint_;
-  DBuf<double> idr00_;
   DBuf<cplx> root_;         // dense top-level systems of all trees
   DBuf<int> rootpiv_, rootinfo_;
   size_t rootvec_total_ = 0;  // sum of the trees' root orders
