@@ -14,6 +14,11 @@ U[0.1, 0.3], N log-uniform in [4096, 65536], k_out U[5, 80], k_in = 1.5 k_out)
 solved together in one context: per-level shared launches, autotuned launch
 variants, factorisation and solve replayed as HIP graphs.  Also reports the
 sum of the same boundaries solved one at a time.
+
+--config 5: the same batch with proxy circles sized by the rank predictor,
+trained on the GPU from ranks the solver measures on one random star per
+seed 1000-1099 (ID tolerances 1e-6 ... 1e-12); compared with the same batch
+without the predictor.
 """
 
 from __future__ import annotations
@@ -227,6 +232,93 @@ def _run_batch(args):
     print(json.dumps(out))
 
 
+def _run_predictor(args):
+    """Batch workload with and without predictor-sized proxy circles."""
+    import torch
+    import workloads
+    from paper_2609_33216_amd import binding, predictor
+
+    t0 = time.perf_counter()
+    feat, rank = predictor.training_set(seeds=range(1000, 1100))
+    t_data = time.perf_counter() - t0
+    print(f"predictor: {len(rank)} training boxes in {t_data:.1f} s", file=sys.stderr, flush=True)
+    wls = workloads.config3_batch(seed=3, count=64)
+    ntot = sum(w.n for w in wls)
+    dev = torch.device("cuda:0")
+    b = torch.zeros(2 * ntot, dtype=torch.complex128, device=dev)
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    s = binding.Solver(0)
+    t0 = time.perf_counter()
+    hist = s.predictor_train(feat, rank, epochs=args.epochs, batch=1024, lr=2e-3, alpha=4.0, seed=0)
+    t_train = time.perf_counter() - t0
+    print(f"predictor: trained {args.epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3g} -> {hist[-1]:.3g}",
+          file=sys.stderr, flush=True)
+    s.configure(graphs=not args.no_graphs, autotune=True)
+    s.assemble_batch([w.boundary() for w in wls], [(w.k0, w.k1, w.eps0, w.eps1) for w in wls], leaf=128,
+                     tol=1e-10, form=binding.MULLER_SYM)
+    s.rhs_plane_wave_batch_device([w.angle for w in wls], b.data_ptr())
+
+    def timed(use_pred):
+        s.configure(predictor=use_pred)
+        for _ in range(max(args.warmup, 2)):
+            s.compress()
+            s.factor()
+            s.solve_device(b.data_ptr(), x.data_ptr())
+        torch.cuda.synchronize()
+        per, tc = [], []
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            s.compress()
+            tc.append(time.perf_counter() - t1)
+            s.factor()
+            s.solve_device(b.data_ptr(), x.data_ptr())
+            torch.cuda.synchronize()
+            per.append(time.perf_counter() - t1)
+        st = s.stats()
+        y = torch.zeros_like(x)
+        s.lib.symhss_matvec_direct(s.h, binding.ctypes.c_void_p(x.data_ptr()),
+                                   binding.ctypes.c_void_p(y.data_ptr()), binding.DEVICE_PTRS)
+        torch.cuda.synchronize()
+        res, o = [], 0
+        for w in wls:
+            res.append(float(torch.linalg.vector_norm(y[o:o + 2 * w.n] - b[o:o + 2 * w.n]) /
+                             torch.linalg.vector_norm(b[o:o + 2 * w.n])))
+            o += 2 * w.n
+        return sum(per) / len(per), sum(tc) / len(tc), st, max(res), x.clone()
+
+    t_base, tc_base, st_base, res_base, x_base = timed(False)
+    print(f"predictor: without {1e3 * t_base:.1f} ms", file=sys.stderr, flush=True)
+    t_pred, tc_pred, st_pred, res_pred, x_pred = timed(True)
+    print(f"predictor: with {1e3 * t_pred:.1f} ms", file=sys.stderr, flush=True)
+    diff = float(torch.linalg.vector_norm(x_pred - x_base) / torch.linalg.vector_norm(x_base))
+    out = {
+        "metric": "HSS compress+factor s/solve & Gentries/s, sym vs nonsym, at 1e-8 rel err",
+        "value": round(t_pred, 6),
+        "unit": "s/solve (whole 64-boundary batch, predictor-sized)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t_pred, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "batch64-stars-seed3+rank-predictor", "boundaries": len(wls), "n_nodes_total": ntot,
+                   "train_seeds": "1000-1099", "train_tols": [1e-6, 1e-8, 1e-10, 1e-12], "leaf": 128,
+                   "tol": 1e-10, "graphs": not args.no_graphs, "parallelism": "1 GPU"},
+        "train_boxes": int(len(rank)), "train_data_s": round(t_data, 3), "train_s": round(t_train, 3),
+        "train_epochs": args.epochs, "train_loss": [float(hist[0]), float(hist[-1])],
+        "without": {"s_per_solve": round(t_base, 6), "t_compress": round(tc_base, 6),
+                    "residual_fp64_direct_max": res_base, "proxy_rows": st_base["proxy_rows"],
+                    "proxy_bytes": st_base["proxy_bytes"]},
+        "with": {"s_per_solve": round(t_pred, 6), "t_compress": round(tc_pred, 6),
+                 "residual_fp64_direct_max": res_pred, "proxy_rows": st_pred["proxy_rows"],
+                 "proxy_bytes": st_pred["proxy_bytes"], "predicted_boxes": st_pred["pred_boxes"],
+                 "fallbacks": st_pred["pred_fallbacks"]},
+        "compress_speedup": round(tc_base / tc_pred, 3),
+        "total_speedup": round(t_base / t_pred, 3),
+        "fallback_rate": round(st_pred["pred_fallbacks"] / max(st_pred["pred_boxes"], 1), 4),
+        "proxy_bytes_saved": st_base["proxy_bytes"] - st_pred["proxy_bytes"],
+        "solution_rel_diff_with_vs_without": diff,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +330,7 @@ def main():
     ap.add_argument("--no-residual", action="store_true")
     ap.add_argument("--no-graphs", action="store_true", help="batch mode: no HIP-graph replay")
     ap.add_argument("--no-single", action="store_true", help="batch mode: skip the one-at-a-time sum")
+    ap.add_argument("--epochs", type=int, default=300, help="predictor mode: training epochs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this path has no multi-GPU mode); got --gpus {args.gpus}",
@@ -246,6 +339,9 @@ def main():
 
     if args.config == 3:
         _run_batch(args)
+        return
+    if args.config == 5:
+        _run_predictor(args)
         return
 
     import numpy as np

@@ -261,6 +261,8 @@ typedef struct {
   int32_t pred_fallbacks;    /* of those, compressed again with the rule's count */
   int64_t proxy_rows;        /* proxy-matrix rows generated (all passes) */
   int64_t proxy_rows_rule;   /* rows the rule's counts would have generated */
+  double proxy_bytes;        /* bytes of the proxy matrices generated (all passes) */
+  double proxy_bytes_rule;   /* bytes with the rule's counts */
 } symhss_stats;
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);

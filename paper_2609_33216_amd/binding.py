@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("n_lu_multi", ctypes.c_int32), ("bytes_kblock", ctypes.c_double),
                 ("graph_replays", ctypes.c_int32), ("tuned_buckets", ctypes.c_int32),
                 ("pred_boxes", ctypes.c_int32), ("pred_fallbacks", ctypes.c_int32),
-                ("proxy_rows", ctypes.c_int64), ("proxy_rows_rule", ctypes.c_int64)]
+                ("proxy_rows", ctypes.c_int64), ("proxy_rows_rule", ctypes.c_int64),
+                ("proxy_bytes", ctypes.c_double), ("proxy_bytes_rule", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_
