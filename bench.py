@@ -15,6 +15,10 @@ solved together in one context: per-level shared launches, autotuned launch
 variants, factorisation and solve replayed as HIP graphs.  Also reports the
 sum of the same boundaries solved one at a time.
 
+--config 4: star r = 1 + 0.25 cos 7t, N = 262144, k = 200 / 300, solved by
+the FP64 path and by the mixed-precision path (FP32 factorisation and
+sweeps, refined against the FP64 HSS product to 1e-10).
+
 --config 5: the same batch with proxy circles sized by the rank predictor,
 trained on the GPU from ranks the solver measures on one random star per
 seed 1000-1099 (ID tolerances 1e-6 ... 1e-12); compared with the same batch
@@ -319,6 +323,92 @@ def _run_predictor(args):
     print(json.dumps(out))
 
 
+def _run_mixed(args):
+    """Star r = 1 + 0.25 cos 7t, N = 262144, k = 200 / 300: FP64 path and the
+    mixed-precision path (FP32 factorisation, FP64 HSS refinement to 1e-10)."""
+    import torch
+    import workloads
+    from paper_2609_33216_amd import binding
+
+    wl = workloads.config4() if args.n4 is None else workloads.scaled_config(workloads.config4(), args.n4)
+    n = wl.n
+    dev = torch.device("cuda:0")
+    b = torch.zeros(2 * n, dtype=torch.complex128, device=dev)
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    s = binding.Solver(0)
+    xw, dxw, ddxw = wl.boundary()
+    s.assemble(xw, dxw, ddxw, wl.k0, wl.k1, wl.eps0, wl.eps1, leaf=wl.leaf, tol=wl.tol, root_max=args.root_max)
+    s.rhs_plane_wave_device(wl.angle, b.data_ptr())
+
+    def run(mixed):
+        s.configure(mixed=mixed)
+        per = []
+        for it in range(args.warmup + args.steps):
+            t0 = time.perf_counter()
+            s.compress()
+            t1 = time.perf_counter()
+            s.factor()
+            t2 = time.perf_counter()
+            s.solve_device(b.data_ptr(), x.data_ptr())
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            st = s.stats()
+            print(f"  {'mixed' if mixed else 'fp64'} step {it}: compress {t1 - t0:.3f} factor {t2 - t1:.3f} "
+                  f"solve {t3 - t2:.3f} s; ranks {st['rank_max']} root {st['root_size']}", file=sys.stderr,
+                  flush=True)
+            if it >= args.warmup:
+                per.append(t3 - t0)
+        return sum(per) / len(per), s.stats(), x.clone()
+
+    print(f"mixed: N={n}; FP64 path", file=sys.stderr, flush=True)
+    t64, st64, x64 = run(False)
+    print(f"mixed: FP64 {1e3 * t64:.1f} ms; mixed path", file=sys.stderr, flush=True)
+    t32, st32, x32 = run(True)
+    print(f"mixed: mixed {1e3 * t32:.1f} ms; residuals", file=sys.stderr, flush=True)
+    # FP32-only iterate
+    s.configure(refine_maxit=1)
+    s.solve_device(b.data_ptr(), x.data_ptr())
+    torch.cuda.synchronize()
+    x1 = x.clone()
+    s.configure(refine_maxit=10)
+
+    def resid(v):
+        y = torch.zeros_like(v)
+        s.lib.symhss_matvec_direct(s.h, binding.ctypes.c_void_p(v.data_ptr()), binding.ctypes.c_void_p(y.data_ptr()),
+                                   binding.DEVICE_PTRS)
+        torch.cuda.synchronize()
+        return float(torch.linalg.vector_norm(y - b) / torch.linalg.vector_norm(b))
+
+    def rdiff(a, c):
+        return float(torch.linalg.vector_norm(a - c) / torch.linalg.vector_norm(c))
+
+    r64 = resid(x64) if not args.no_residual else None
+    r32 = resid(x32) if not args.no_residual else None
+    out = {
+        "metric": "HSS compress+factor s/solve & Gentries/s, sym vs nonsym, at 1e-8 rel err",
+        "value": round(t32, 6),
+        "unit": "s/solve (mixed precision, refined to 1e-10)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t32, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128", "data": "synthetic",
+        "config": {"workload": wl.name, "n_nodes": n, "unknowns": 2 * n, "k_out": wl.k0, "k_in": wl.k1,
+                   "leaf": wl.leaf, "tol": wl.tol, "form": "symmetric one-sided ID", "parallelism": "1 GPU"},
+        "fp64": {"s_per_solve": round(t64, 6), "t_compress": round(st64["t_compress"], 6),
+                 "t_factor": round(st64["t_factor"], 6), "t_solve": round(st64["t_solve"], 6),
+                 "residual_fp64_direct": r64},
+        "mixed": {"s_per_solve": round(t32, 6), "t_compress": round(st32["t_compress"], 6),
+                  "t_factor": round(st32["t_factor"], 6), "t_solve": round(st32["t_solve"], 6),
+                  "refine_iters": st32["refine_iters"], "hss_residual_first_fp32_solve": st32["fp32_residual"],
+                  "hss_residual_refined": st32["refine_residual"], "residual_fp64_direct": r32},
+        "err_fp32_only_vs_fp64_hss": rdiff(x1, x64),
+        "err_refined_vs_fp64_hss": rdiff(x32, x64),
+        "speedup_mixed_vs_fp64": round(t64 / t32, 3),
+        "ranks_max_per_level": st32["rank_max"], "root_size": st32["root_size"],
+        "device_bytes_fp64": st64["device_bytes"], "device_bytes_mixed": st32["device_bytes"],
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +421,9 @@ def main():
     ap.add_argument("--no-graphs", action="store_true", help="batch mode: no HIP-graph replay")
     ap.add_argument("--no-single", action="store_true", help="batch mode: skip the one-at-a-time sum")
     ap.add_argument("--epochs", type=int, default=300, help="predictor mode: training epochs")
+    ap.add_argument("--n4", type=int, default=None, help="mixed mode: another N for the seven-arm star")
+    ap.add_argument("--root-max", type=int, default=8192,
+                    help="mixed mode: largest dense top-level system (sum of ranks)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this path has no multi-GPU mode); got --gpus {args.gpus}",
@@ -342,6 +435,9 @@ def main():
         return
     if args.config == 5:
         _run_predictor(args)
+        return
+    if args.config == 4:
+        _run_mixed(args)
         return
 
     import numpy as np

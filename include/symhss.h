@@ -167,12 +167,27 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
  *       the same result.
  *  SYMHSS_OPT_PERSISTENT [-1] ID grid: 0 one workgroup per matrix, 1 a
  *       persistent grid taking matrices from a work queue, -1 automatic.
+ *  SYMHSS_OPT_PREDICTOR   [0] 1: proxy counts from the rank predictor (below).
+ *  SYMHSS_OPT_PROXY_MARGIN [16] proxy points added to the predicted rank.
+ *  SYMHSS_OPT_PRECISION   [0] 1: mixed precision.  The IDs and every kernel
+ *       block stay FP64; the generated blocks are kept, and with the FP64
+ *       interpolation matrices form the FP64 HSS representation.  The
+ *       factorisation (diagonal-block LUs, X, A~, top-level systems) and the
+ *       solve sweeps run in complex FP32 on the FP32 roundings, and
+ *       symhss_solve refines: x += FP32 solve of r, r = b - A_HSS x in FP64,
+ *       until |r| / |b| <= 10^-digits (every right-hand side) or the
+ *       iteration limit.  Changing it requires a new symhss_factor.
+ *  SYMHSS_OPT_REFINE_DIGITS [10] the refinement target 10^-digits (1..15).
+ *  SYMHSS_OPT_REFINE_MAXIT  [10] the refinement iteration limit (1..100).
  * EINVAL for an unknown option or value. */
 #define SYMHSS_OPT_GRAPHS 0
 #define SYMHSS_OPT_AUTOTUNE 1
 #define SYMHSS_OPT_PERSISTENT 2
 #define SYMHSS_OPT_PREDICTOR 3
 #define SYMHSS_OPT_PROXY_MARGIN 4
+#define SYMHSS_OPT_PRECISION 5
+#define SYMHSS_OPT_REFINE_DIGITS 6
+#define SYMHSS_OPT_REFINE_MAXIT 7
 symhss_status symhss_configure(symhss_ctx *ctx, int32_t option, int64_t value);
 
 /* Rank predictor (sizes fixed before the factorisation runs, Section 4.3):
@@ -229,6 +244,12 @@ symhss_status symhss_box_table(symhss_ctx *ctx, int64_t *count, float *feat, int
 symhss_status symhss_predictor_grad(symhss_ctx *ctx, const float *weights, const float *feat, const float *rank,
                                     int64_t n, float alpha, float *grad, float *loss);
 
+/* Verification (mixed precision, after factor): y = A_HSS x, the FP64
+ * product of the compressed representation that drives the refinement;
+ * x, y: 2N complex, host pointers unless SYMHSS_DEVICE_PTRS.  ESTATE in FP64
+ * mode (the generators are not kept there). */
+symhss_status symhss_hss_matvec(symhss_ctx *ctx, const symhss_z *x, symhss_z *y, int32_t flags);
+
 /* Statistics of the last assemble/compress/factor/solve. */
 typedef struct {
   int32_t levels;            /* L */
@@ -263,6 +284,11 @@ typedef struct {
   int64_t proxy_rows_rule;   /* rows the rule's counts would have generated */
   double proxy_bytes;        /* bytes of the proxy matrices generated (all passes) */
   double proxy_bytes_rule;   /* bytes with the rule's counts */
+  /* mixed precision (last solve) */
+  int32_t refine_iters;      /* FP32 solves performed */
+  int32_t pad0;
+  double fp32_residual;      /* |b - A_HSS x| / |b| after the first FP32 solve */
+  double refine_residual;    /* the same after the last one */
 } symhss_stats;
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);

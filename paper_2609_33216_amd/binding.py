@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsymhss.so")
 MULLER_SYM, MULLER_BASE, MULLER_SYM_TWOSIDED = 0, 1, 2
 DEVICE_PTRS = 1
 OPT_GRAPHS, OPT_AUTOTUNE, OPT_PERSISTENT, OPT_PREDICTOR, OPT_PROXY_MARGIN = 0, 1, 2, 3, 4
+OPT_PRECISION, OPT_REFINE_DIGITS, OPT_REFINE_MAXIT = 5, 6, 7
 
 _STATUS = {
     0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ESINGULAR", 6: "ERANK",
@@ -59,7 +60,9 @@ class Stats(ctypes.Structure):
                 ("graph_replays", ctypes.c_int32), ("tuned_buckets", ctypes.c_int32),
                 ("pred_boxes", ctypes.c_int32), ("pred_fallbacks", ctypes.c_int32),
                 ("proxy_rows", ctypes.c_int64), ("proxy_rows_rule", ctypes.c_int64),
-                ("proxy_bytes", ctypes.c_double), ("proxy_bytes_rule", ctypes.c_double)]
+                ("proxy_bytes", ctypes.c_double), ("proxy_bytes_rule", ctypes.c_double),
+                ("refine_iters", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("fp32_residual", ctypes.c_double), ("refine_residual", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_
@@ -78,7 +81,7 @@ EXPORTS = [
     "symhss_eval_bessel", "symhss_matvec_direct", "symhss_get_stats", "symhss_box_query",
     "symhss_assemble_batch", "symhss_rhs_plane_wave_batch", "symhss_configure",
     "symhss_predictor_train", "symhss_predictor_load", "symhss_predictor_get", "symhss_predictor_predict",
-    "symhss_predictor_grad", "symhss_box_table",
+    "symhss_predictor_grad", "symhss_box_table", "symhss_hss_matvec",
 ]
 
 PREDICTOR_WEIGHTS = 8845
@@ -133,6 +136,7 @@ def load(path: str | None = None):
         "symhss_predictor_predict": ([vp, vp, i64, vp], ctypes.c_int),
         "symhss_predictor_grad": ([vp, vp, vp, vp, i64, ctypes.c_float, vp, vp], ctypes.c_int),
         "symhss_box_table": ([vp, ctypes.POINTER(i64), vp, vp, vp], ctypes.c_int),
+        "symhss_hss_matvec": ([vp, vp, vp, i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -183,10 +187,12 @@ class Solver:
             raise SymhssError(st, self.lib.symhss_last_error(self.h).decode())
 
     def configure(self, graphs: bool | None = None, autotune: bool | None = None, persistent: int | None = None,
-                  predictor: bool | None = None, proxy_margin: int | None = None):
+                  predictor: bool | None = None, proxy_margin: int | None = None, mixed: bool | None = None,
+                  refine_digits: int | None = None, refine_maxit: int | None = None):
         """Execution options (see symhss_configure)."""
         for opt, v in ((OPT_GRAPHS, graphs), (OPT_AUTOTUNE, autotune), (OPT_PERSISTENT, persistent),
-                       (OPT_PREDICTOR, predictor), (OPT_PROXY_MARGIN, proxy_margin)):
+                       (OPT_PREDICTOR, predictor), (OPT_PROXY_MARGIN, proxy_margin), (OPT_PRECISION, mixed),
+                       (OPT_REFINE_DIGITS, refine_digits), (OPT_REFINE_MAXIT, refine_maxit)):
             if v is not None:
                 self._check(self.lib.symhss_configure(self.h, opt, int(v)))
 
@@ -329,6 +335,12 @@ class Solver:
         out = np.zeros((len(z), 5), dtype=np.float64)
         self._check(self.lib.symhss_eval_bessel(self.h, len(z), _ptr(z), _ptr(out)))
         return out
+
+    def hss_matvec(self, x):
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.zeros_like(x)
+        self._check(self.lib.symhss_hss_matvec(self.h, _ptr(x), _ptr(y), 0))
+        return y
 
     def matvec_direct(self, x):
         x = np.ascontiguousarray(x, dtype=np.complex128)

@@ -197,6 +197,13 @@ symhss_status symhss_box_table(symhss_ctx* ctx, int64_t* count, float* feat, int
   });
 }
 
+symhss_status symhss_hss_matvec(symhss_ctx* ctx, const symhss_z* x, symhss_z* y, int32_t flags) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    if (!x || !y) throw std::invalid_argument("null vector");
+    s.hss_matvec(x, y, flags);
+  });
+}
+
 symhss_status symhss_get_stats(const symhss_ctx* ctx, symhss_stats* out) {
   if (!ctx || !ctx->s || !out) return SYMHSS_EINVAL;
   *out = ctx->s->stats();

@@ -45,6 +45,36 @@ __host__ __device__ inline cplx cdiv(cplx a, cplx b) {
   return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
 }
 
+// Complex FP32 (mixed-precision factorisation) with the same operations.
+struct cplxf {
+  float re, im;
+};
+__host__ __device__ inline cplxf operator+(cplxf a, cplxf b) { return {a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cplxf operator-(cplxf a, cplxf b) { return {a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cplxf operator-(cplxf a) { return {-a.re, -a.im}; }
+__host__ __device__ inline cplxf operator*(cplxf a, cplxf b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cplxf operator*(double s, cplxf a) { return {(float)s * a.re, (float)s * a.im}; }
+__host__ __device__ inline cplxf conj(cplxf a) { return {a.re, -a.im}; }
+__host__ __device__ inline float abs2(cplxf a) { return a.re * a.re + a.im * a.im; }
+__host__ __device__ inline void fma_acc(cplxf& a, cplxf b, cplxf c) {
+  a.re = fmaf(b.re, c.re, fmaf(-b.im, c.im, a.re));
+  a.im = fmaf(b.re, c.im, fmaf(b.im, c.re, a.im));
+}
+__host__ __device__ inline void fma_conj_acc(cplxf& a, cplxf b, cplxf c) {
+  a.re = fmaf(b.re, c.re, fmaf(b.im, c.im, a.re));
+  a.im = fmaf(b.re, c.im, fmaf(-b.im, c.re, a.im));
+}
+__host__ __device__ inline cplxf cdiv(cplxf a, cplxf b) {
+  if (fabsf(b.re) >= fabsf(b.im)) {
+    const float r = b.im / b.re, d = b.re + b.im * r;
+    return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  }
+  const float r = b.re / b.im, d = b.im + b.re * r;
+  return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+
 // Boundary and proxy points, structure of arrays.  Index < n_boundary is a
 // boundary node (the nodes of all boundaries of a batch, one after another);
 // larger indices are proxy points of the current level.

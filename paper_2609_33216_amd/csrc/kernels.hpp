@@ -2,6 +2,8 @@
 // the host driver.
 #pragma once
 
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace symhss {
@@ -27,51 +29,7 @@ struct InterpDesc {
   int ldo, row0, col0, transpose;
 };
 
-struct LuDesc {
-  cplx* A;
-  int n;     // order of the factored block
-  int ncol;  // total columns (n + appended right-hand sides)
-  int lda;
-  int* ipiv;
-  int* info;
-};
-
-struct GemmDesc {
-  const cplx* A;
-  const cplx* B;
-  cplx* C;
-  int m, n, k;
-  int lda, ldb, ldc;
-  double alpha, beta;  // real scalars: C = beta C + alpha A B
-};
-
-struct CopyDesc {
-  // dst[dmap[i] + ldd * c] = src[smap[i] + lds * c], i < rows, c < cols;
-  // a null map means the identity.
-  const cplx* src;
-  cplx* dst;
-  const int* smap;
-  const int* dmap;
-  int rows, cols, lds, ldd;
-};
-
-struct Scatter2Desc {
-  // dst[rmap[i] + ldd * cmap[j]] = src[i + lds * j]
-  const cplx* src;
-  cplx* dst;
-  const int* rmap;
-  const int* cmap;
-  int m, n, lds, ldd;
-};
-
-// Solve with a factored block for a few right-hand sides held apart from the
-// factor: B := D^{-1} B using the pivots and L, U of k_lu_fused.
-struct SolveDesc {
-  const cplx* LU;
-  const int* ipiv;
-  cplx* B;
-  int n, lda, ldb, nrhs;
-};
+#include "dense_types.inc"
 
 // kernel-block generation (kblock.hip)
 // media: device array indexed by KJob::med
@@ -101,14 +59,27 @@ void launch_equalise_ranks(hipStream_t st, int npairs, const int* ia, const int*
 __global__ void k_zero_i32(int* p, int n);
 
 // batched dense algebra (dense.hip)
-void launch_lu_fused(hipStream_t st, const LuDesc* d, int count);
-// host-looped multi-workgroup variant; nmax / ncolmax / nrhsmax bound n, ncol, ncol - n
-void launch_lu_multi(hipStream_t st, const LuDesc* d, int count, int nmax, int ncolmax, int nrhsmax);
-void launch_gemm_batched(hipStream_t st, const GemmDesc* d, int count, int mmax, int nmax);
-void launch_lu_solve(hipStream_t st, const SolveDesc* d, int count);
-void launch_copy_batched(hipStream_t st, const CopyDesc* d, int count, long maxelems);
-void launch_scatter2_batched(hipStream_t st, const Scatter2Desc* d, int count, long maxelems);
-void launch_zero(hipStream_t st, cplx* p, long count);
-void launch_set_identity(hipStream_t st, const LuDesc* d, int count, int nmax);
+#include "dense_api.inc"
+
+// mixed precision (mixed.hip): FP64 -> FP32 block copies and FP64 refinement vectors
+struct ConvDesc {
+  // dst[i + ldd c] = (FP32) src[i + lds c], i < rows, c < cols
+  const cplx* src;
+  cplxf* dst;
+  int rows, cols, lds, ldd;
+};
+void launch_convert_batched(hipStream_t st, const ConvDesc* d, int count, long maxelems);
+void launch_round_vec(hipStream_t st, const cplx* x, cplxf* y, long n);
+void launch_add_vec(hipStream_t st, cplx* x, const cplxf* d, long n);
+void launch_sub_vec(hipStream_t st, const cplx* b, const cplx* y, cplx* r, long n);
+void launch_col_norm2(hipStream_t st, const cplx* v, long n, long ld, int ncols, double* out);
+
+// the same in complex FP32 (dense32.hip)
+namespace f32 {
+using cplx = cplxf;
+__host__ __device__ inline cplx mk(double r, double i) { return cplx{(float)r, (float)i}; }
+#include "dense_types.inc"
+#include "dense_api.inc"
+}  // namespace f32
 
 }  // namespace symhss

@@ -107,6 +107,7 @@ struct Box {
   size_t off_R = 0, off_L = 0, off_aug1 = 0, off_aug2 = 0;
   size_t off_piv1 = 0, off_piv2 = 0;
   size_t off_s = 0, off_k = 0;  // prefix sums of s and k (solve buffers, maps)
+  size_t off_gen = 0;           // mixed precision: s x s generator block
 };
 
 // All boxes at one height of the forest (height 0: leaves).  The boxes of a
@@ -126,6 +127,11 @@ struct Level {
                          // positions of their unknowns in that system
   // solve buffers
   DBuf<cplx> F, G, Ft, Z;
+  // mixed precision: FP64 generator blocks (leaf D, parent sibling blocks,
+  // s x s per box) for the FP64 HSS product, and the FP32 factorisation
+  DBuf<cplx> gen;
+  DBuf<f32::cplx> aug1f, aug2f, interpf;
+  DBuf<f32::cplx> Ff, Gf, Ftf, Zf;
   size_t s_total = 0, k_total = 0;
 };
 
@@ -168,6 +174,7 @@ class Solver {
   void matvec_direct(const symhss_z* x, symhss_z* y, int flags);
   void box_query(int level, int box, int what, int64_t* count, void* out);
   void configure(int what, int64_t value);
+  void hss_matvec(const symhss_z* x, symhss_z* y, int flags);
   Mlp& predictor() { return mlp_; }
   void box_table(int64_t* count, float* feat, int32_t* rank, int32_t* info) const;
   symhss_stats stats() const {
@@ -217,6 +224,16 @@ class Solver {
   void run_lu(const LuDesc* d, int count, int nmax, int ncolmax, int nrhsmax, cplx* data, size_t data_elems,
               int* info, int ninfo, double flops);
   void solve_enqueue(const cplx* db, cplx* dx, int nrhs);
+  struct Sweep64;
+  struct Sweep32;
+  template <class S>
+  void solve_sweep(const typename S::C* db, typename S::C* dx, int nrhs);
+  // mixed precision: FP32 factorisation, FP64 HSS product, refinement
+  void factor_level_mixed(int h);
+  void factor_root_mixed();
+  void hss_matvec_enqueue(const cplx* x, cplx* y);
+  void solve_mixed(const cplx* db, cplx* dx, int nrhs);
+  void ensure_sweep_buffers(int nrhs, bool fp32);
   // kernel-block launches
   struct KBatch {
     std::vector<KJob> jobs;
@@ -263,6 +280,14 @@ class Solver {
   DBuf<int> rootpiv_, rootinfo_;
   size_t rootvec_total_ = 0;  // sum of the trees' root orders
   DBuf<cplx> rootF_, rootG_;
+  // mixed precision
+  int precision_ = 0;               // 0 FP64, 1 FP32 factorisation + FP64 refinement
+  int refine_digits_ = 10, refine_maxit_ = 10;
+  DBuf<cplx> root_gen_;             // off-diagonal blocks of the top-level systems (FP64)
+  DBuf<f32::cplx> rootf_, rootFf_, rootGf_;
+  DBuf<cplx> rwork_;                // residual, product, correction vectors
+  DBuf<f32::cplx> rworkf_;
+  DBuf<double> norms_;
   DBuf<cplx> vec_;  // staging of b / x for host-pointer solves
   // execution options (symhss_configure)
   int use_graphs_ = 0, autotune_ = 0, persistent_ = -1;

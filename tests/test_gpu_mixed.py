@@ -1,0 +1,104 @@
+"""Mixed precision on the GPU: FP32 factorisation and solve sweeps refined
+against the FP64 HSS product.
+
+* The FP64 HSS product equals the oracle's dense product A x within the
+  compression error (tol 1e-10): bar 1e-8 relative.
+* The refined solution matches the oracle's dense LU solution within 1e-8
+  and the FP64 path's solution within 1e-9, for the symmetric one-sided form,
+  the unscaled two-sided baseline and a batch of boundaries; the first (FP32
+  only) iterate is stated and must be worse than the refined one.
+* Several right-hand sides refine together."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense
+from tests.gpu_common import make_solver, oracle_system, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _wl(n=2048):
+    return workloads.scaled_config(workloads.config2(), n, leaf=64)
+
+
+def test_hss_product_vs_oracle():
+    wl = _wl()
+    _, _, A, b = oracle_system(wl)
+    s = make_solver(wl)
+    s.configure(mixed=True)
+    s.compress()
+    s.factor()
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(b.shape) + 1j * rng.standard_normal(b.shape)
+    y = s.hss_matvec(x)
+    e = rel(y, A @ x)
+    print("HSS product rel err", e)
+    assert e < 1e-8
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_refined_solution(form):
+    wl = _wl()
+    _, _, A, b = oracle_system(wl, row_scaled=form != 1)
+    xd = dense.solve_dense(A, b)
+    s64 = make_solver(wl, form=form)
+    s64.compress()
+    s64.factor()
+    x64 = s64.solve(b)
+    s = make_solver(wl, form=form)
+    s.configure(mixed=True)
+    s.compress()
+    s.factor()
+    x = s.solve(b)
+    st = s.stats()
+    print("form", form, "iters", st["refine_iters"], "fp32 residual", st["fp32_residual"], "refined",
+          st["refine_residual"], "err vs dense", rel(x, xd), "vs fp64", rel(x, x64))
+    assert st["refine_residual"] <= 1e-10
+    assert st["refine_iters"] >= 2
+    assert st["fp32_residual"] > 10 * st["refine_residual"]
+    assert rel(x, xd) < 1e-8
+    assert rel(x, x64) < 1e-9
+
+
+def test_refined_multiple_rhs_and_single_iteration():
+    wl = _wl(1536)
+    _, _, A, b = oracle_system(wl)
+    rng = np.random.default_rng(8)
+    B = np.stack([b, rng.standard_normal(b.shape) + 1j * rng.standard_normal(b.shape)], axis=1)
+    s = make_solver(wl)
+    s.configure(mixed=True)
+    s.compress()
+    s.factor()
+    X = s.solve(B)
+    assert rel(X, dense.solve_dense(A, B)) < 1e-8
+    s.configure(refine_maxit=1)
+    x1 = s.solve(b)
+    st = s.stats()
+    e1 = rel(x1, dense.solve_dense(A, b))
+    print("FP32-only iterate: residual", st["fp32_residual"], "error", e1)
+    assert st["refine_iters"] == 1
+    assert 1e-9 < e1 < 1e-3
+
+
+def test_mixed_batch():
+    base = workloads.config2()
+    wls = [dataclasses.replace(base, name=f"m{i}", curve_params=(("amp", 0.15 + 0.05 * i), ("arms", 3 + 2 * i)),
+                               n=n, k0=k, k1=1.5 * k, angle=0.4 * i, leaf=64)
+           for i, (n, k) in enumerate([(900, 10.0), (1600, 22.0), (2200, 35.0)])]
+    from paper_2609_33216_amd import binding
+    s = binding.Solver(0)
+    s.assemble_batch([w.boundary() for w in wls], [(w.k0, w.k1, w.eps0, w.eps1) for w in wls], leaf=64)
+    s.configure(mixed=True)
+    b = s.rhs_plane_wave_batch([w.angle for w in wls])
+    s.compress()
+    s.factor()
+    x = s.solve(b)
+    o = 0
+    for w in wls:
+        _, _, A, bo = oracle_system(w)
+        assert rel(x[o:o + 2 * w.n], dense.solve_dense(A, bo)) < 1e-8
+        o += 2 * w.n
