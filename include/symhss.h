@@ -289,6 +289,7 @@ typedef struct {
   int32_t pad0;
   double fp32_residual;      /* |b - A_HSS x| / |b| after the first FP32 solve */
   double refine_residual;    /* the same after the last one */
+  double t_compress_wait;    /* of t_compress, seconds the host waited for the GPU */
 } symhss_stats;
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);

@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("proxy_rows", ctypes.c_int64), ("proxy_rows_rule", ctypes.c_int64),
                 ("proxy_bytes", ctypes.c_double), ("proxy_bytes_rule", ctypes.c_double),
                 ("refine_iters", ctypes.c_int32), ("pad0", ctypes.c_int32),
-                ("fp32_residual", ctypes.c_double), ("refine_residual", ctypes.c_double)]
+                ("fp32_residual", ctypes.c_double), ("refine_residual", ctypes.c_double),
+                ("t_compress_wait", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_

@@ -300,7 +300,10 @@ class Solver {
   uint64_t ssig_ = 0;
   int sseen_ = 0;
   hipGraphExec_t sgraph_ = nullptr;
-  size_t last_factor_upload_ = 0, last_solve_upload_ = 0;  // descriptor bytes of the last eager runs
+  size_t last_factor_upload_ = 0, last_solve_upload_ = 0;
+  double sync_wait_ = 0.0;  // host seconds spent waiting for the stream
+  int* pinned_ = nullptr;   // pinned host staging of the ID results
+  size_t pinned_cap_ = 0;  // descriptor bytes of the last eager runs
   void drop_graphs();
   // autotuner: size bucket -> chosen variant
   std::vector<std::pair<uint64_t, int>> tuned_;
