@@ -77,10 +77,10 @@ def _workload(cfg: int):
     raise SystemExit(f"unknown config {cfg}")
 
 
-def _run_form(s, wl, form, steps, warmup, b, x, torch):
+def _run_form(s, wl, form, steps, warmup, b, x, torch, root_max=0):
     x_, dx_, ddx_ = wl.boundary()
     s.assemble(x_, dx_, ddx_, wl.k0, wl.k1, wl.eps0, wl.eps1, leaf=wl.leaf, tol=wl.tol, form=form,
-               n_proxy=wl.n_proxy if wl.n_proxy > 0 else 64, proxy_ratio=wl.proxy_ratio)
+               n_proxy=wl.n_proxy if wl.n_proxy > 0 else 64, proxy_ratio=wl.proxy_ratio, root_max=root_max)
     s.rhs_plane_wave_device(wl.angle, b.data_ptr())
     for _ in range(warmup):
         s.compress()
@@ -422,9 +422,12 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="batch mode: skip the one-at-a-time sum")
     ap.add_argument("--epochs", type=int, default=300, help="predictor mode: training epochs")
     ap.add_argument("--n4", type=int, default=None, help="mixed mode: another N for the seven-arm star")
-    ap.add_argument("--root-max", type=int, default=8192,
-                    help="mixed mode: largest dense top-level system (sum of ranks)")
+    ap.add_argument("--root-max", type=int, default=None,
+                    help="largest dense top-level system (sum of ranks); default 2048, 8192 for --config 4")
     args = ap.parse_args()
+    args.root_max_given = args.root_max is not None
+    if args.root_max is None:
+        args.root_max = 8192 if args.config == 4 else 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this path has no multi-GPU mode); got --gpus {args.gpus}",
               file=sys.stderr)
@@ -452,7 +455,8 @@ def main():
     torch.cuda.synchronize()  # the solver queues on its own stream
     s = binding.Solver(0)
 
-    t_sym, st, per = _run_form(s, wl, binding.MULLER_SYM, args.steps, args.warmup, b, x, torch)
+    rm = args.root_max if args.root_max_given else 0
+    t_sym, st, per = _run_form(s, wl, binding.MULLER_SYM, args.steps, args.warmup, b, x, torch, rm)
     resid = None
     if not args.no_residual:
         y = torch.zeros_like(x)
@@ -524,7 +528,7 @@ def main():
         out["kernel_rooflines"] = rl
 
     if not args.no_base:
-        t_base, stb, _ = _run_form(s, wl, binding.MULLER_BASE, 1, 1, b, x, torch)
+        t_base, stb, _ = _run_form(s, wl, binding.MULLER_BASE, 1, 1, b, x, torch, rm)
         out["nonsym"] = {"s_per_solve": round(t_base, 6), "t_compress": round(stb["t_compress"], 6),
                          "t_factor": round(stb["t_factor"], 6),
                          "entries": int(stb["entries_compress"] + stb["entries_factor"])}

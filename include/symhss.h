@@ -75,7 +75,7 @@ typedef struct {
   int32_t n_proxy;     /* minimum proxy points per circle (e.g. 64) */
   int32_t root_max;    /* top of the tree: compression stops at the first level (from the
                           leaves) whose boxes' ranks sum to at most root_max, and that level's
-                          compressed system is factored densely; 0: default 1536; < 0: compress
+                          compressed system is factored densely; 0: default 2048; < 0: compress
                           every level down to level 1 (two boxes at the root) */
   double proxy_ratio;  /* proxy radius / box radius (e.g. 1.5) */
 } symhss_opts;

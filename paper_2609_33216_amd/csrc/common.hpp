@@ -45,6 +45,13 @@ __host__ __device__ inline cplx cdiv(cplx a, cplx b) {
   return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
 }
 
+// 1 / z as conj(z) / |z|^2: one real division (pivots of the LU panels,
+// whose magnitudes are far from the overflow range of |z|^2).
+__host__ __device__ inline cplx crecip(cplx z) {
+  const double d = 1.0 / (z.re * z.re + z.im * z.im);
+  return {z.re * d, -z.im * d};
+}
+
 // Complex FP32 (mixed-precision factorisation) with the same operations.
 struct cplxf {
   float re, im;
@@ -73,6 +80,11 @@ __host__ __device__ inline cplxf cdiv(cplxf a, cplxf b) {
   }
   const float r = b.re / b.im, d = b.im + b.re * r;
   return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+
+__host__ __device__ inline cplxf crecip(cplxf z) {
+  const float d = 1.0f / (z.re * z.re + z.im * z.im);
+  return {z.re * d, -z.im * d};
 }
 
 // Boundary and proxy points, structure of arrays.  Index < n_boundary is a
