@@ -19,6 +19,10 @@ sum of the same boundaries solved one at a time.
 the FP64 path and by the mixed-precision path (FP32 factorisation and
 sweeps, refined against the FP64 HSS product to 1e-10).
 
+--config 6: the paper's fixed-rank schedule (k_L = 30, growth a per level)
+on the five-arm star at N = 8192 ... 131072: time and factorisation flops
+against N, with fitted exponents (O(N) for a < 2^(1/3)).
+
 --config 5: the same batch with proxy circles sized by the rank predictor,
 trained on the GPU from ranks the solver measures on one random star per
 seed 1000-1099 (ID tolerances 1e-6 ... 1e-12); compared with the same batch
@@ -409,6 +413,61 @@ def _run_mixed(args):
     print(json.dumps(out))
 
 
+def _run_scaling(args):
+    """Fixed-rank schedule k_l = a^(L - l) k_L (Section 4.3, Theorem 1): time and
+    factorisation flops against N on the five-arm star, k = 50 / 75."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2609_33216_amd import binding
+
+    ns = [8192, 16384, 32768, 65536, 131072]
+    dev = torch.device("cuda:0")
+    res = {}
+    for a in (1.0, 1.15, 1.3):
+        rows = []
+        for n in ns:
+            wl = workloads.scaled_config(workloads.config2(), n)
+            b = torch.zeros(2 * n, dtype=torch.complex128, device=dev)
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            s = binding.Solver(0)
+            xw, dxw, ddxw = wl.boundary()
+            s.assemble(xw, dxw, ddxw, wl.k0, wl.k1, wl.eps0, wl.eps1, leaf=128, tol=1e-10, root_max=-1)
+            s.configure(rank_leaf=30, rank_scale=a)
+            s.rhs_plane_wave_device(wl.angle, b.data_ptr())
+            per = []
+            for it in range(args.warmup + args.steps):
+                t0 = time.perf_counter()
+                s.compress()
+                s.factor()
+                s.solve_device(b.data_ptr(), x.data_ptr())
+                torch.cuda.synchronize()
+                if it >= args.warmup:
+                    per.append(time.perf_counter() - t0)
+            st = s.stats()
+            rows.append({"n": n, "s_per_solve": round(sum(per) / len(per), 6), "t_factor": round(st["t_factor"], 6),
+                         "flops_lu": st["flops_lu_batched"] + st["flops_lu_multi"], "root_size": st["root_size"]})
+            print(f"scaling: a={a} N={n} {1e3 * rows[-1]['s_per_solve']:.1f} ms", file=sys.stderr, flush=True)
+            s.close()
+        lx = np.log([r["n"] for r in rows])
+        res[str(a)] = {"runs": rows,
+                       "exponent_time": round(float(np.polyfit(lx, np.log([r["s_per_solve"] for r in rows]), 1)[0]), 3),
+                       "exponent_flops": round(float(np.polyfit(lx, np.log([r["flops_lu"] for r in rows]), 1)[0]), 3),
+                       "theorem_exponent": 1.0 if a < 2 ** (1 / 3) else round(3 * np.log2(a), 3)}
+    big = res["1.15"]["runs"][-1]
+    out = {
+        "metric": "HSS compress+factor s/solve & Gentries/s, sym vs nonsym, at 1e-8 rel err",
+        "value": big["s_per_solve"], "unit": "s/solve (fixed ranks k_L = 30, a = 1.15, N = 131072)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * big["s_per_solve"], 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "star5-k50-75 fixed-rank sweep", "n": ns, "leaf": 128, "k_L": 30,
+                   "a": [1.0, 1.15, 1.3], "parallelism": "1 GPU"},
+        "scaling_by_a": res,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +500,9 @@ def main():
         return
     if args.config == 4:
         _run_mixed(args)
+        return
+    if args.config == 6:
+        _run_scaling(args)
         return
 
     import numpy as np

@@ -179,6 +179,12 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
  *       iteration limit.  Changing it requires a new symhss_factor.
  *  SYMHSS_OPT_REFINE_DIGITS [10] the refinement target 10^-digits (1..15).
  *  SYMHSS_OPT_REFINE_MAXIT  [10] the refinement iteration limit (1..100).
+ *  SYMHSS_OPT_RANK_LEAF    [0] k_L > 0: fixed-rank schedule (Section 4.3):
+ *       every ID of a box at level l of its boundary's tree (leaves at level
+ *       L) has rank min(round(k_L a^(L - l)), columns, rows) per half, instead
+ *       of the tolerance rule; 0: tolerance mode.
+ *  SYMHSS_OPT_RANK_SCALE [1000] the growth a per level, times 1000 (1000..4000).
+ *       Both require a new symhss_compress.
  * EINVAL for an unknown option or value. */
 #define SYMHSS_OPT_GRAPHS 0
 #define SYMHSS_OPT_AUTOTUNE 1
@@ -188,6 +194,8 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
 #define SYMHSS_OPT_PRECISION 5
 #define SYMHSS_OPT_REFINE_DIGITS 6
 #define SYMHSS_OPT_REFINE_MAXIT 7
+#define SYMHSS_OPT_RANK_LEAF 8
+#define SYMHSS_OPT_RANK_SCALE 9
 symhss_status symhss_configure(symhss_ctx *ctx, int32_t option, int64_t value);
 
 /* Rank predictor (sizes fixed before the factorisation runs, Section 4.3):

@@ -270,6 +270,8 @@ class Solver {
   std::vector<double> hk_;       // curvature at the nodes (predictor features)
   Mlp mlp_;
   int use_predictor_ = 0, proxy_margin_ = 16;
+  int rank_leaf_ = 0;        // fixed-rank schedule: k_L per half (0: tolerance mode)
+  double rank_scale_ = 1.0;  // and the growth a per level
   DBuf<double> geo_;             // px, py, nx, ny, w, kappa, each of capacity cap_
   size_t cap_ = 0;
   symhss_opts opts_{};

@@ -1,0 +1,75 @@
+"""Fixed-rank schedule (Section 4.3): ranks k_l = a^(L - l) k_L per half.
+
+* Every compressed box carries exactly the scheduled rank (capped by its
+  matrix), for the symmetric and the two-sided forms.
+* With the paper's own schedule (k_L = 30, a = 1.15) the solution of the
+  unit-circle workload matches the dense oracle.
+* Theorem 1: the factorisation's flop count (the stats' algorithmic count of
+  the LU kernels, from the actual block sizes) grows linearly in N for
+  a < 2^(1/3) and faster for a > 2^(1/3)."""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense
+from tests.gpu_common import make_solver, oracle_system, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_scheduled_ranks(form):
+    wl = workloads.scaled_config(workloads.config2(), 4096, leaf=64)
+    s = make_solver(wl, form=form, root_max=-1)
+    kL, a = 20, 1.15
+    s.configure(rank_leaf=kL, rank_scale=a)
+    s.compress()
+    st = s.stats()
+    L = st["levels"]
+    for lev in range(1, L + 1):
+        h = L - lev
+        want = int(round(kL * a ** h))
+        nb = 2 ** lev
+        for b in range(0, nb, max(1, nb // 8)):
+            kcq, kcu, krq, kru = s.box_query(lev, b, 15)
+            ncq = len(s.box_query(lev, b, 0))
+            ncu = len(s.box_query(lev, b, 1))
+            assert kcq == min(want, ncq) and kcu == min(want, ncu), (lev, b, kcq, kcu, want)
+            assert (krq, kru) == (kcq, kcu)
+
+
+def test_paper_schedule_accuracy():
+    wl = workloads.config1()
+    _, _, A, b = oracle_system(wl)
+    s = make_solver(wl)
+    s.configure(rank_leaf=30, rank_scale=1.15)
+    s.compress()
+    s.factor()
+    x = s.solve(b)
+    e = rel(x, dense.solve_dense(A, b))
+    print("k_L = 30, a = 1.15: error vs dense", e, "ranks", s.stats()["rank_max"])
+    assert e < 1e-8
+
+
+def _flops(n, kL, a):
+    wl = workloads.scaled_config(workloads.config2(), n, leaf=64)
+    s = make_solver(wl, root_max=-1)
+    s.configure(rank_leaf=kL, rank_scale=a)
+    s.compress()
+    s.factor()
+    st = s.stats()
+    return st["flops_lu_batched"] + st["flops_lu_multi"]
+
+
+def test_theorem1_flop_scaling():
+    ns = [2048, 4096, 8192, 16384]
+    r = {}
+    for a in (1.0, 1.15, 1.5):
+        f = [_flops(n, 12, a) for n in ns]
+        r[a] = [f[i + 1] / f[i] for i in range(len(f) - 1)]
+        print("a", a, "flops", [f"{v:.3g}" for v in f], "ratios per doubling", [round(v, 3) for v in r[a]])
+    # O(N): flops double with N; above 2^(1/3) the top levels take over
+    assert all(1.8 < v < 2.25 for v in r[1.0])
+    assert all(1.8 < v < 2.4 for v in r[1.15])
+    assert r[1.5][-1] > r[1.0][-1] + 0.3
