@@ -48,11 +48,11 @@ MI355X_HBM_TBS = 8.0
 # on a plain 512 MiB copy (fetch x2.0, write x1.0).  Valid only while the
 # kernel's source is the one profiled: keyed by the SHA-256 prefix of its file.
 MEASURED_TRAFFIC = {
-    "k_cpqr": {"source": "cpqr.hip", "sha": "bc2af5c2f8b06665", "bytes": 2.5617e9,
+    "k_cpqr": {"source": "cpqr.hip", "sha": "0b76eff22489f474", "bytes": 3.087e+09,
                "profile": "profiles/k_cpqr_star5-n32768.md"},
-    "k_lu_fused": {"source": "dense.hip", "sha": "68e391844583578b", "bytes": 0.76656e9,
+    "k_lu_fused": {"source": "dense_body.inc", "sha": "e894b095366fc3e4", "bytes": 7.645e+08,
                    "profile": "profiles/k_lu_fused_star5-n32768.md"},
-    "k_kblock": {"source": "kblock.hip", "sha": "20fba2554b30b7fb", "bytes": 0.062492e9,
+    "k_kblock": {"source": "kblock.hip", "sha": "8d35d53fffcbe977", "bytes": 7.427e+07,
                  "profile": "profiles/k_kblock_star5-n32768.md"},
 }
 
