@@ -23,6 +23,10 @@ sweeps, refined against the FP64 HSS product to 1e-10).
 on the five-arm star at N = 8192 ... 131072: time and factorisation flops
 against N, with fitted exponents (O(N) for a < 2^(1/3)).
 
+--config 7: the paper's speedup experiment on one GPU: kite, eps = 1 / 3,
+omega = 2, fixed ranks k_L = 30, a = 1.15, 6400 ... 1638400 DOF, symmetric
+one-sided form against the unscaled two-sided Base.
+
 --config 5: the same batch with proxy circles sized by the rank predictor,
 trained on the GPU from ranks the solver measures on one random star per
 seed 1000-1099 (ID tolerances 1e-6 ... 1e-12); compared with the same batch
@@ -468,6 +472,74 @@ def _run_scaling(args):
     print(json.dumps(out))
 
 
+def _run_kite(args):
+    """The paper's speedup experiment on one GPU: kite, eps0 = 1, eps1 = 3, plane
+    wave along x1, fixed ranks k_L = 30, a = 1.15, 6400 ... 1638400 DOF; the
+    symmetric one-sided form against the unscaled two-sided Base."""
+    import math
+    import numpy as np
+    import torch
+    from workloads.curves import sample_curve
+    from paper_2609_33216_amd import binding
+
+    omega = 2.0
+    k0, k1 = omega, omega * math.sqrt(3.0)
+    dofs = [6400 * 2 ** i for i in range(9)] if args.kite_max is None else \
+        [d for d in (6400 * 2 ** i for i in range(9)) if d <= args.kite_max]
+    dev = torch.device("cuda:0")
+    rows = []
+    for dof in dofs:
+        n = dof // 2
+        x, dx, ddx = sample_curve("kite", n)
+        b = torch.zeros(2 * n, dtype=torch.complex128, device=dev)
+        xv = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        rec = {"dof": dof}
+        sols = {}
+        for name, form in (("sym", binding.MULLER_SYM), ("base", binding.MULLER_BASE)):
+            s = binding.Solver(0)
+            s.assemble(x, dx, ddx, k0, k1, 1.0, 3.0, leaf=128, tol=1e-10, form=form)
+            s.configure(rank_leaf=30, rank_scale=1.15)
+            s.rhs_plane_wave_device(0.0, b.data_ptr())
+            per = []
+            for it in range(args.warmup + args.steps):
+                t0 = time.perf_counter()
+                s.compress()
+                s.factor()
+                s.solve_device(b.data_ptr(), xv.data_ptr())
+                torch.cuda.synchronize()
+                if it >= args.warmup:
+                    per.append(time.perf_counter() - t0)
+            st = s.stats()
+            rec[name] = {"s_per_solve": round(float(np.median(per)), 6), "t_compress": round(st["t_compress"], 6),
+                         "t_factor": round(st["t_factor"], 6), "t_solve": round(st["t_solve"], 6),
+                         "entries": int(st["entries_compress"] + st["entries_factor"])}
+            sols[name] = xv.clone()
+            s.close()
+        rec["speedup_sym_vs_base"] = round(rec["base"]["s_per_solve"] / rec["sym"]["s_per_solve"], 3)
+        rec["speedup_compress"] = round(rec["base"]["t_compress"] / rec["sym"]["t_compress"], 3)
+        rec["rel_diff_sym_base"] = float(torch.linalg.vector_norm(sols["sym"] - sols["base"]) /
+                                         torch.linalg.vector_norm(sols["base"]))
+        rows.append(rec)
+        print(f"kite: DOF {dof}: sym {1e3 * rec['sym']['s_per_solve']:.1f} ms, base "
+              f"{1e3 * rec['base']['s_per_solve']:.1f} ms, x{rec['speedup_sym_vs_base']}", file=sys.stderr, flush=True)
+    mean = float(np.mean([r["speedup_sym_vs_base"] for r in rows]))
+    big = rows[-1]
+    out = {
+        "metric": "HSS compress+factor s/solve & Gentries/s, sym vs nonsym, at 1e-8 rel err",
+        "value": big["sym"]["s_per_solve"], "unit": f"s/solve (kite, {big['dof']} DOF, symmetric)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * big["sym"]["s_per_solve"], 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "kite DOF sweep", "curve": "kite x = (cos t + 0.65 cos 2t - 0.65, 1.5 sin t)",
+                   "omega": omega, "eps": [1.0, 3.0], "k_L": 30, "a": 1.15, "leaf": 128, "dof": dofs,
+                   "parallelism": "1 GPU"},
+        "runs": rows,
+        "mean_speedup_sym_vs_base": round(mean, 3),
+        "paper_context": "1.436 mean over 9 sizes on one 192-core CPU node (Table 4)",
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -481,6 +553,7 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="batch mode: skip the one-at-a-time sum")
     ap.add_argument("--epochs", type=int, default=300, help="predictor mode: training epochs")
     ap.add_argument("--n4", type=int, default=None, help="mixed mode: another N for the seven-arm star")
+    ap.add_argument("--kite-max", type=int, default=None, help="kite sweep: largest DOF")
     ap.add_argument("--root-max", type=int, default=None,
                     help="largest dense top-level system (sum of ranks); default 2048, 8192 for --config 4")
     args = ap.parse_args()
@@ -503,6 +576,9 @@ def main():
         return
     if args.config == 6:
         _run_scaling(args)
+        return
+    if args.config == 7:
+        _run_kite(args)
         return
 
     import numpy as np

@@ -73,3 +73,21 @@ def test_theorem1_flop_scaling():
     assert all(1.8 < v < 2.25 for v in r[1.0])
     assert all(1.8 < v < 2.4 for v in r[1.15])
     assert r[1.5][-1] > r[1.0][-1] + 0.3
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_kite_fixed_rank_vs_dense(form):
+    # the kite of the paper's speedup experiment (eps 1 / 3, omega = 2,
+    # plane wave along x1) with its fixed-rank schedule, at a size the dense
+    # oracle solves in seconds; ragged leaves (N = 1600)
+    import math
+    wl = workloads.Workload("kite-n1600", "kite", (), 1600, 2.0, 2.0 * math.sqrt(3.0), 0.0, leaf=128)
+    _, _, A, b = oracle_system(wl, row_scaled=form != 1)
+    s = make_solver(wl, form=form)
+    s.configure(rank_leaf=30, rank_scale=1.15)
+    s.compress()
+    s.factor()
+    x = s.solve(b)
+    e = rel(x, dense.solve_dense(A, b))
+    print("kite form", form, "error vs dense", e)
+    assert e < 1e-8
