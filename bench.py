@@ -233,6 +233,9 @@ def _run_batch(args):
         "boundaries_per_s": round(len(wls) / t_batch, 3),
         "step_times": [round(v, 6) for v in per],
         "t_compress": round(st["t_compress"], 6), "t_factor": round(st["t_factor"], 6),
+        "t_compress_host": round(st["t_compress"] - st["t_compress_wait"], 6),
+        "kernel_seconds": {"kblock": round(st["t_kblock_compress"] + st["t_kblock_factor"], 6),
+                           "id": round(st["t_id"], 6), "lu": round(st["t_lu"], 6)},
         "t_solve": round(st["t_solve"], 6),
         "entries": int(ent),
         "gentries_per_s_whole_step": round(ent / t_batch / 1e9, 3),
@@ -551,6 +554,8 @@ def main():
     ap.add_argument("--no-residual", action="store_true")
     ap.add_argument("--no-graphs", action="store_true", help="batch mode: no HIP-graph replay")
     ap.add_argument("--no-single", action="store_true", help="batch mode: skip the one-at-a-time sum")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="factor each level after compress instead of on a second stream during it")
     ap.add_argument("--epochs", type=int, default=300, help="predictor mode: training epochs")
     ap.add_argument("--n4", type=int, default=None, help="mixed mode: another N for the seven-arm star")
     ap.add_argument("--kite-max", type=int, default=None, help="kite sweep: largest DOF")
@@ -592,6 +597,7 @@ def main():
     x = torch.zeros(2 * n, dtype=torch.complex128, device=dev)
     torch.cuda.synchronize()  # the solver queues on its own stream
     s = binding.Solver(0)
+    s.configure(pipeline=not args.no_pipeline)
 
     rm = args.root_max if args.root_max_given else 0
     t_sym, st, per = _run_form(s, wl, binding.MULLER_SYM, args.steps, args.warmup, b, x, torch, rm)
@@ -622,7 +628,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "curve": f"{wl.curve} {dict(wl.curve_params)}", "n_nodes": n,
                    "unknowns": 2 * n, "k_out": wl.k0, "k_in": wl.k1, "leaf": wl.leaf, "tol": wl.tol,
-                   "form": "symmetric one-sided ID", "parallelism": "1 GPU"},
+                   "form": "symmetric one-sided ID", "pipelined_factor": not args.no_pipeline,
+                   "parallelism": "1 GPU"},
         "t_compress": round(st["t_compress"], 6),
         "t_compress_host": round(st["t_compress"] - st["t_compress_wait"], 6),
         "t_factor": round(st["t_factor"], 6),

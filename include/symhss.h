@@ -157,8 +157,9 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
 
 /* Execution options; value in brackets is the default.
  *  SYMHSS_OPT_GRAPHS      [0] 1: the second time a compressed structure is
- *       factored, its launch sequence is captured as a HIP graph and every
- *       later factorisation of the same structure replays it; likewise a
+ *       factored (with SYMHSS_OPT_PIPELINE off), its launch sequence is
+ *       captured as a HIP graph and every later factorisation of the same
+ *       structure replays it; likewise a
  *       device-pointer solve repeated with the same vectors and nrhs.  Kernel
  *       timings in the statistics are not collected for replays.
  *  SYMHSS_OPT_AUTOTUNE    [0] 1: the first ID and LU launch of each size bucket
@@ -185,6 +186,11 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
  *       of the tolerance rule; 0: tolerance mode.
  *  SYMHSS_OPT_RANK_SCALE [1000] the growth a per level, times 1000 (1000..4000).
  *       Both require a new symhss_compress.
+ *  SYMHSS_OPT_PIPELINE    [1] 1: in FP64, symhss_compress already queues
+ *       each level's factorisation on a second stream as soon as the level's
+ *       IDs are known (it overlaps the planning of the next level);
+ *       symhss_factor then adds the top-level systems and waits.  Such a
+ *       factorisation is not captured as a graph (solves still are).
  * EINVAL for an unknown option or value. */
 #define SYMHSS_OPT_GRAPHS 0
 #define SYMHSS_OPT_AUTOTUNE 1
@@ -196,6 +202,7 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
 #define SYMHSS_OPT_REFINE_MAXIT 7
 #define SYMHSS_OPT_RANK_LEAF 8
 #define SYMHSS_OPT_RANK_SCALE 9
+#define SYMHSS_OPT_PIPELINE 10
 symhss_status symhss_configure(symhss_ctx *ctx, int32_t option, int64_t value);
 
 /* Rank predictor (sizes fixed before the factorisation runs, Section 4.3):

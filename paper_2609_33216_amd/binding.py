@@ -19,7 +19,7 @@ MULLER_SYM, MULLER_BASE, MULLER_SYM_TWOSIDED = 0, 1, 2
 DEVICE_PTRS = 1
 OPT_GRAPHS, OPT_AUTOTUNE, OPT_PERSISTENT, OPT_PREDICTOR, OPT_PROXY_MARGIN = 0, 1, 2, 3, 4
 OPT_PRECISION, OPT_REFINE_DIGITS, OPT_REFINE_MAXIT = 5, 6, 7
-OPT_RANK_LEAF, OPT_RANK_SCALE = 8, 9
+OPT_RANK_LEAF, OPT_RANK_SCALE, OPT_PIPELINE = 8, 9, 10
 
 _STATUS = {
     0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ESINGULAR", 6: "ERANK",
@@ -191,12 +191,12 @@ class Solver:
     def configure(self, graphs: bool | None = None, autotune: bool | None = None, persistent: int | None = None,
                   predictor: bool | None = None, proxy_margin: int | None = None, mixed: bool | None = None,
                   refine_digits: int | None = None, refine_maxit: int | None = None,
-                  rank_leaf: int | None = None, rank_scale: float | None = None):
+                  rank_leaf: int | None = None, rank_scale: float | None = None, pipeline: bool | None = None):
         """Execution options (see symhss_configure); rank_scale is the growth a (e.g. 1.15)."""
         for opt, v in ((OPT_GRAPHS, graphs), (OPT_AUTOTUNE, autotune), (OPT_PERSISTENT, persistent),
                        (OPT_PREDICTOR, predictor), (OPT_PROXY_MARGIN, proxy_margin), (OPT_PRECISION, mixed),
                        (OPT_REFINE_DIGITS, refine_digits), (OPT_REFINE_MAXIT, refine_maxit),
-                       (OPT_RANK_LEAF, rank_leaf),
+                       (OPT_RANK_LEAF, rank_leaf), (OPT_PIPELINE, pipeline),
                        (OPT_RANK_SCALE, None if rank_scale is None else round(1000 * rank_scale))):
             if v is not None:
                 self._check(self.lib.symhss_configure(self.h, opt, int(v)))

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <chrono>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -215,6 +216,9 @@ class Solver {
   void box_features_of(int h, const Box& B, float* f) const;
   // factor pieces
   void factor_layout();
+  void factor_layout_level(int h);
+  void factor_layout_root();
+  void enqueue_on_factor_stream(const std::function<void()>& f);
   void factor_level(int h);
   void factor_root();
   void factor_enqueue();
@@ -253,6 +257,7 @@ class Solver {
   void timer_begin(int what, double work = 0.0);
   void timer_end();
   void collect_timers();
+  void collect_timers(std::vector<TimerPair>& list);
   void sync();
 
   int device_;  // HIP device the context was created on
@@ -311,8 +316,17 @@ class Solver {
   std::vector<std::pair<uint64_t, int>> tuned_;
   int tuned_choice(uint64_t key) const;
   DBuf<cplx> tune_backup_;
+  DBuf<cplx> tune_backup_lu_;  // LU trials run on the factor stream
   DBuf<int> queue_;
   std::vector<TimerPair> timers_;
+  std::vector<TimerPair> ftimers_;           // launches on the factor stream
+  std::vector<TimerPair>* tl_ = &timers_;    // where timer_begin records
+  // pipelining: per-level factor work on a second stream during compress
+  hipStream_t fst_ = nullptr;
+  hipEvent_t cev_ = nullptr;
+  Uploader fup2_;
+  int pipeline_opt_ = 1;
+  bool pipelined_ = false;
   std::vector<hipEvent_t> event_pool_;
   symhss_stats stats_{};
 };

@@ -8,7 +8,11 @@ autotuner and HIP-graph replay of factorisations and solves.
 * Graph replays are checked on every replay against the eager result of the
   same structure (bit-identical: same kernels, same data), with eager work
   and synchronisation between replays, and a changed structure is not
-  served by a stale graph."""
+  served by a stale graph.
+* Pipelined factorisation (each level factored on a second stream while the
+  next level is compressed) gives bit-identical solutions to factoring after
+  compress, also with the autotuner, two compresses in a row, and a switch to
+  mixed precision between compress and factor."""
 
 import numpy as np
 import pytest
@@ -58,12 +62,13 @@ def test_autotuned_matches():
     assert rel(x1, dense.solve_dense(A, b)) < 1e-8
 
 
-def test_graph_replay_every_replay_matches_eager():
+@pytest.mark.parametrize("pipeline", [False, True])
+def test_graph_replay_every_replay_matches_eager(pipeline):
     import torch
     wl = _wl()
     _, _, A, b = oracle_system(wl)
     s = make_solver(wl)
-    s.configure(graphs=True)
+    s.configure(graphs=True, pipeline=pipeline)
     dev = torch.device("cuda:0")
     bd = torch.from_numpy(b).to(dev)
     xd = torch.zeros_like(bd)
@@ -85,7 +90,8 @@ def test_graph_replay_every_replay_matches_eager():
         del junk
         xd.zero_()
         torch.cuda.synchronize()
-    assert s.stats()["graph_replays"] >= 4  # factor replays (2) + solve replays (2)
+    # factor replays (2, unless pipelined) + solve replays (2)
+    assert s.stats()["graph_replays"] >= (2 if pipeline else 4)
 
 
 def test_graph_not_reused_after_structure_change():
@@ -130,3 +136,35 @@ def test_batch_with_graphs_and_autotune():
         xt = xs[2][o:o + 2 * wl.n]
         o += 2 * wl.n
         assert rel(xt, dense.solve_dense(A, bo)) < 1e-8
+
+
+def test_pipelined_factor_bit_identical():
+    wl = _wl(3000)
+    _, _, A, b = oracle_system(wl)
+    s0 = make_solver(wl)
+    s0.configure(pipeline=False)
+    x0 = _solve(s0, b)
+    s1 = make_solver(wl)
+    s1.configure(pipeline=True)
+    x1 = _solve(s1, b)
+    assert np.array_equal(x0, x1)
+    assert rel(x1, dense.solve_dense(A, b)) < 1e-8
+    assert s1.stats()["n_lu"] == s0.stats()["n_lu"]
+    # two compresses before one factor; a second factor of the same compress
+    s1.compress()
+    s1.compress()
+    s1.factor()
+    assert np.array_equal(s1.solve(b), x0)
+    s1.factor()
+    assert np.array_equal(s1.solve(b), x0)
+    # autotuned LU trials run on the factor stream
+    s2 = make_solver(wl)
+    s2.configure(pipeline=True, autotune=True)
+    for _ in range(2):
+        x2 = _solve(s2, b)
+        assert rel(x2, x0) < 1e-12
+    # precision switched after a pipelined compress: factor redoes the levels
+    s1.compress()
+    s1.configure(mixed=True)
+    s1.factor()
+    assert rel(s1.solve(b), x0) < 1e-9
