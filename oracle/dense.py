@@ -1,4 +1,5 @@
-"""Right-hand side and dense LU solve of the Muller-like system.
+"""Right-hand sides and dense LU solve of the Muller-like, PMCHWT and
+Burton-Miller systems.
 
 Right-hand side (eq. symmetric_muller): [-eps0 W u_in; W q_in] with
 q_in = d u_in / d nu.  The paper prints (1/eps0) W q_in in the second row;
@@ -27,9 +28,21 @@ def plane_wave(geom: Geometry, k0: float, angle: float):
     return uin, qin
 
 
-def rhs(geom: Geometry, med: Medium, uin, qin, row_scaled: bool = True):
+def rhs(geom: Geometry, med: Medium, uin, qin, row_scaled: bool = True, eq: str = "muller"):
+    """Right-hand side of the chosen system (row-scaled by W or not).
+
+    muller: [-eps0 u_in; q_in]; pmchwt (eq. naive_pmchwt):
+    [-u_in; q_in / eps0]; bm (eq. bm): [-u_in - alpha q_in; 0], alpha = i/k0.
+    """
     sc = geom.w if row_scaled else np.ones(geom.n)
-    return np.concatenate([-med.eps0 * sc * uin, sc * qin])
+    if eq == "muller":
+        return np.concatenate([-med.eps0 * sc * uin, sc * qin])
+    if eq == "pmchwt":
+        return np.concatenate([-sc * uin, sc * qin / med.eps0])
+    if eq == "bm":
+        al = 1j / med.k0
+        return np.concatenate([-sc * (uin + al * qin), np.zeros(geom.n, dtype=np.complex128)])
+    raise ValueError(f"unknown system {eq!r}")
 
 
 def solve_dense(A, b):

@@ -22,8 +22,25 @@ ln(h/2pi) + ln|x'_i| = ln(w_i/2pi).  The small-argument expansions
   N_k0-N_k1  = -(Delta/4pi) ln r + i Delta/8 - (Delta/4pi)(gamma - 1/2)
                - (1/4pi)(k0^2 ln(k0/2) - k1^2 ln(k1/2)) + O(r^2 ln r),
   Delta = k0^2 - k1^2,
-give the corrected diagonals below.  The individual N_k is hypersingular and
-never needs a diagonal here: only N_k0 - N_k1 appears in the system.
+give the corrected diagonals below.
+
+The individual N_k (needed by the PMCHWT and Burton-Miller systems) is
+hypersingular.  Along the curve, in the parameter t around t_i, its kernel
+times |y'| is A/t^2 + C ln|t| + (smooth), A = 1/(2 pi |x'_i|), with no 1/t
+term (the Laplace part 1/(2 pi s^2) + kappa^2/(24 pi) in arclength s, pulled
+back, gains only a constant).  The punctured trapezoidal sum of
+phi(t)/t^2 exceeds the finite-part integral by 2 zeta(2) phi(0)/h -
+(h/2) phi''(0) + O(h^3): the one-point rule removes the first term and keeps
+the second, which is why N_k converges at first order only (Section 3.1,
+estimate for N_k).  The diagonal is
+  N~_k = -pi/(6 w_i^2) + kappa_i^2/(24 pi) + i k^2/8
+         - (k^2/4pi)(ln(k/2) + gamma - 1/2 + ln(w_i/2pi)),
+from N_k = 1/(2 pi r^2) + kappa^2/(24 pi) - (k^2/4pi) ln r + i k^2/8
+- (k^2/4pi)(ln(k/2) + gamma - 1/2) + o(1); the difference of two such
+diagonals is the N_k0 - N_k1 value above.  A constant that depends on how
+the parameter runs along the curve (the Schwarzian derivative of the
+arclength, which needs the third derivative of the curve) is left out: it
+weighs O(h), as does the rule's own error.
 
 System (eq. symmetric_muller, block form eq. block_A), unknowns [q; u]:
   A11 = -(eps0^2 S_k0 - eps1^2 S_k1)
@@ -34,6 +51,25 @@ with row-scaled operators [Z]_ij = w_i Z~(x_i, y_j) w_j.  The unscaled
 baseline (eq. naive_muller) uses [Z']_ij = Z~(x_i, y_j) w_j and free terms
 -/+ (eps0 + eps1)/2 I.  Entries are formed as (w_i w_j) * K so that the
 scaled matrix is symmetric up to the free terms to the last bit.
+
+PMCHWT (eq. naive_pmchwt, row-scaled: eq. symmetric_pmchwt), same unknowns:
+  A11 = -(eps0 S_k0 + eps1 S_k1)    A12 = D_k0 + D_k1
+  A21 = D*_k0 + D*_k1               A22 = -(N_k0 / eps0 + N_k1 / eps1)
+(the free terms cancel, so the row-scaled matrix is exactly symmetric).
+
+Burton-Miller (eq. bm), alpha = i / k0.  The paper orders the unknowns
+[u; q]; here the columns are permuted to [q; u] so that every system shares
+one layout (rows: combined exterior equation, interior equation):
+  A11 = -eps0 (S_k0 + alpha (D*_k0 + I/2))   A12 = D_k0 - I/2 + alpha N_k0
+  A21 = -eps1 S_k1                           A22 = D_k1 + I/2
+The printed system carries +alpha eps0 (D*_k0 + I/2): with the exterior
+equations (D_k0 - I/2) u - eps0 S_k0 q = -u_in and
+eps0 (D*_k0 + I/2) q - N_k0 u = q_in (the second rows of eq. naive_muller),
+only the combination exterior - alpha * (normal derivative) reproduces both
+the printed +alpha N_k0 and the printed right-hand side -u_in - alpha q_in,
+and that combination has -alpha eps0 (D*_k0 + I/2).  This module takes that
+reading (one sign); the printed sign does not converge to the transmission
+solution (pinned in the tests).
 """
 
 from __future__ import annotations
@@ -144,6 +180,101 @@ def corrected_diagonals(w, kappa, med: Medium):
     return gdiag(k0), gdiag(k1), dd, nd
 
 
+def n_single_diagonal(w, kappa, k: float):
+    """One-point corrected diagonal of the hypersingular N_k (see module text)."""
+    w = np.asarray(w, dtype=np.float64)
+    ell = np.log(w / (2.0 * np.pi))
+    kap = np.asarray(kappa, dtype=np.float64)
+    return (-np.pi / (6.0 * w * w) + kap * kap / (24.0 * np.pi) + 0.125j * k * k
+            - k * k / (4.0 * np.pi) * (np.log(k / 2.0) + EULER_GAMMA - 0.5 + ell))
+
+
+def _diag_pairs(obs: PointSet, src: PointSet, same):
+    diag = (obs.gid[:, None] == src.gid[None, :]) & (obs.gid[:, None] >= 0)
+    if np.any(same & ~diag):
+        raise ValueError("coincident points that are not the same boundary node")
+    return np.nonzero(diag)
+
+
+def _weights(obs: PointSet, src: PointSet, shape, row_scaled: bool):
+    if row_scaled:
+        return obs.w[:, None] * src.w[None, :]
+    return np.broadcast_to(src.w[None, :], shape)
+
+
+def pmchwt_blocks(obs: PointSet, src: PointSet, med: Medium, row_scaled: bool = True):
+    """A11, A12, A21, A22 of eq. symmetric_pmchwt (row-scaled) or eq. naive_pmchwt."""
+    e0, e1 = med.eps0, med.eps1
+    G0, Dy0, Dx0, N0, same = layer_kernels(obs, src, med.k0)
+    G1, Dy1, Dx1, N1, _ = layer_kernels(obs, src, med.k1)
+    K11 = -(e0 * G0 + e1 * G1)
+    K12 = Dy0 + Dy1
+    K21 = Dx0 + Dx1
+    K22 = -(N0 / e0 + N1 / e1)
+    io, js = _diag_pairs(obs, src, same)
+    if len(io):
+        g0, g1, dd, _ = corrected_diagonals(obs.w[io], obs.kappa[io], med)
+        n0 = n_single_diagonal(obs.w[io], obs.kappa[io], med.k0)
+        n1 = n_single_diagonal(obs.w[io], obs.kappa[io], med.k1)
+        K11[io, js] = -(e0 * g0 + e1 * g1)
+        K12[io, js] = dd + dd
+        K21[io, js] = dd + dd
+        K22[io, js] = -(n0 / e0 + n1 / e1)
+    ww = _weights(obs, src, K11.shape, row_scaled)
+    return ww * K11, ww * K12, ww * K21, ww * K22
+
+
+def bm_alpha(med: Medium) -> complex:
+    """Burton-Miller coupling constant alpha = i / k0 (Section 6.1)."""
+    return 1j / med.k0
+
+
+def bm_blocks(obs: PointSet, src: PointSet, med: Medium, row_scaled: bool = False):
+    """A11, A12, A21, A22 of eq. bm with the columns in [q; u] order.
+
+    row_scaled=False is the printed (unscaled) system; True multiplies each
+    row by w_i (same solution)."""
+    e0, e1 = med.eps0, med.eps1
+    al = bm_alpha(med)
+    G0, Dy0, Dx0, N0, same = layer_kernels(obs, src, med.k0)
+    G1, Dy1, _, _, _ = layer_kernels(obs, src, med.k1)
+    K11 = -e0 * (G0 + al * Dx0)
+    K12 = Dy0 + al * N0
+    K21 = -e1 * G1
+    K22 = Dy1.copy()
+    io, js = _diag_pairs(obs, src, same)
+    free = np.zeros(len(io))
+    if len(io):
+        g0, g1, dd, _ = corrected_diagonals(obs.w[io], obs.kappa[io], med)
+        n0 = n_single_diagonal(obs.w[io], obs.kappa[io], med.k0)
+        K11[io, js] = -e0 * (g0 + al * dd)
+        K12[io, js] = dd + al * n0
+        K21[io, js] = -e1 * g1
+        K22[io, js] = dd
+        free = 0.5 * (obs.w[io] if row_scaled else np.ones(len(io)))
+    ww = _weights(obs, src, K11.shape, row_scaled)
+    A11, A12, A21, A22 = ww * K11, ww * K12, ww * K21, ww * K22
+    if len(io):
+        A11[io, js] -= al * e0 * free
+        A12[io, js] -= free
+        A22[io, js] += free
+    return A11, A12, A21, A22
+
+
+EQUATIONS = ("muller", "pmchwt", "bm")
+
+
+def system_blocks(obs: PointSet, src: PointSet, med: Medium, row_scaled: bool = True, eq: str = "muller"):
+    """The four sub-blocks of the chosen system between obs and src points."""
+    if eq == "muller":
+        return muller_blocks(obs, src, med, row_scaled)
+    if eq == "pmchwt":
+        return pmchwt_blocks(obs, src, med, row_scaled)
+    if eq == "bm":
+        return bm_blocks(obs, src, med, row_scaled)
+    raise ValueError(f"unknown system {eq!r}")
+
+
 def muller_blocks(obs: PointSet, src: PointSet, med: Medium, row_scaled: bool = True):
     """The four sub-blocks A11, A12, A21, A22 between obs and src points.
 
@@ -186,14 +317,14 @@ def muller_blocks(obs: PointSet, src: PointSet, med: Medium, row_scaled: bool = 
     return A11, A12, A21, A22
 
 
-def assemble(geom: Geometry, med: Medium, row_scaled: bool = True) -> np.ndarray:
+def assemble(geom: Geometry, med: Medium, row_scaled: bool = True, eq: str = "muller") -> np.ndarray:
     """Dense 2N x 2N matrix in the paper's block order [q; u]."""
     ps = PointSet.boundary(geom)
-    A11, A12, A21, A22 = muller_blocks(ps, ps, med, row_scaled)
+    A11, A12, A21, A22 = system_blocks(ps, ps, med, row_scaled, eq)
     return np.block([[A11, A12], [A21, A22]])
 
 
-def entries(geom: Geometry, med: Medium, rows, cols, row_scaled: bool = True) -> np.ndarray:
+def entries(geom: Geometry, med: Medium, rows, cols, row_scaled: bool = True, eq: str = "muller") -> np.ndarray:
     """A[rows][:, cols] of the 2N x 2N system without forming all of A.
 
     rows/cols index the unknowns: i < N is the q-equation / q-unknown of node
@@ -204,7 +335,7 @@ def entries(geom: Geometry, med: Medium, rows, cols, row_scaled: bool = True) ->
     cols = np.asarray(cols, dtype=np.int64)
     rp, rb = rows % n, rows // n
     cp, cb = cols % n, cols // n
-    blocks = muller_blocks(PointSet.boundary(geom, rp), PointSet.boundary(geom, cp), med, row_scaled)
+    blocks = system_blocks(PointSet.boundary(geom, rp), PointSet.boundary(geom, cp), med, row_scaled, eq)
     out = np.empty((len(rows), len(cols)), dtype=np.complex128)
     for bi in (0, 1):
         for bj in (0, 1):
@@ -240,5 +371,15 @@ def ndiff_operator(geom: Geometry, k0: float, k1: float, row_scaled: bool = True
     _, _, _, nd = corrected_diagonals(geom.w, geom.kappa, Medium(k0, k1))
     i = np.arange(geom.n)
     Z[i, i] = nd
+    ww = geom.w[:, None] * geom.w[None, :] if row_scaled else np.broadcast_to(geom.w[None, :], Z.shape)
+    return ww * Z
+
+
+def n_single_operator(geom: Geometry, k: float, row_scaled: bool = True):
+    """The hypersingular N_k with its one-point corrected diagonal."""
+    ps = PointSet.boundary(geom)
+    _, _, _, Z, _ = layer_kernels(ps, ps, k)
+    i = np.arange(geom.n)
+    Z[i, i] = n_single_diagonal(geom.w, geom.kappa, k)
     ww = geom.w[:, None] * geom.w[None, :] if row_scaled else np.broadcast_to(geom.w[None, :], Z.shape)
     return ww * Z
