@@ -25,7 +25,7 @@ against N, with fitted exponents (O(N) for a < 2^(1/3)).
 
 --config 7: the paper's speedup experiment on one GPU: kite, eps = 1 / 3,
 omega = 2, fixed ranks k_L = 30, a = 1.15, 6400 ... 1638400 DOF, symmetric
-one-sided form against the unscaled two-sided Base.
+one-sided form and Burton-Miller against the unscaled two-sided Base.
 
 --config 5: the same batch with proxy circles sized by the rank predictor,
 trained on the GPU from ranks the solver measures on one random star per
@@ -234,6 +234,7 @@ def _run_batch(args):
         "step_times": [round(v, 6) for v in per],
         "t_compress": round(st["t_compress"], 6), "t_factor": round(st["t_factor"], 6),
         "t_compress_host": round(st["t_compress"] - st["t_compress_wait"], 6),
+        "host_seconds": {k: round(st["t_host_" + k], 6) for k in ("plan", "ids", "post", "factor")},
         "kernel_seconds": {"kblock": round(st["t_kblock_compress"] + st["t_kblock_factor"], 6),
                            "id": round(st["t_id"], 6), "lu": round(st["t_lu"], 6)},
         "t_solve": round(st["t_solve"], 6),
@@ -478,7 +479,8 @@ def _run_scaling(args):
 def _run_kite(args):
     """The paper's speedup experiment on one GPU: kite, eps0 = 1, eps1 = 3, plane
     wave along x1, fixed ranks k_L = 30, a = 1.15, 6400 ... 1638400 DOF; the
-    symmetric one-sided form against the unscaled two-sided Base."""
+    symmetric one-sided form and Burton-Miller (two-sided) against the
+    unscaled two-sided Base (Table 4's three columns)."""
     import math
     import numpy as np
     import torch
@@ -499,7 +501,10 @@ def _run_kite(args):
         torch.cuda.synchronize()
         rec = {"dof": dof}
         sols = {}
-        for name, form in (("sym", binding.MULLER_SYM), ("base", binding.MULLER_BASE)):
+        forms = [("sym", binding.MULLER_SYM), ("base", binding.MULLER_BASE)]
+        if not args.no_bm:
+            forms.append(("bm", binding.BURTON_MILLER))
+        for name, form in forms:
             s = binding.Solver(0)
             s.assemble(x, dx, ddx, k0, k1, 1.0, 3.0, leaf=128, tol=1e-10, form=form)
             s.configure(rank_leaf=30, rank_scale=1.15)
@@ -523,10 +528,19 @@ def _run_kite(args):
         rec["speedup_compress"] = round(rec["base"]["t_compress"] / rec["sym"]["t_compress"], 3)
         rec["rel_diff_sym_base"] = float(torch.linalg.vector_norm(sols["sym"] - sols["base"]) /
                                          torch.linalg.vector_norm(sols["base"]))
+        if "bm" in rec:
+            rec["speedup_bm_vs_base"] = round(rec["base"]["s_per_solve"] / rec["bm"]["s_per_solve"], 3)
+            # Burton-Miller's hypersingular N_k0 converges at O(h): its
+            # solution differs from the Muller-like one by that error
+            rec["rel_diff_bm_base"] = float(torch.linalg.vector_norm(sols["bm"] - sols["base"]) /
+                                            torch.linalg.vector_norm(sols["base"]))
         rows.append(rec)
         print(f"kite: DOF {dof}: sym {1e3 * rec['sym']['s_per_solve']:.1f} ms, base "
-              f"{1e3 * rec['base']['s_per_solve']:.1f} ms, x{rec['speedup_sym_vs_base']}", file=sys.stderr, flush=True)
+              f"{1e3 * rec['base']['s_per_solve']:.1f} ms, x{rec['speedup_sym_vs_base']}"
+              + (f"; bm {1e3 * rec['bm']['s_per_solve']:.1f} ms, x{rec['speedup_bm_vs_base']}" if "bm" in rec else ""),
+              file=sys.stderr, flush=True)
     mean = float(np.mean([r["speedup_sym_vs_base"] for r in rows]))
+    mean_bm = float(np.mean([r["speedup_bm_vs_base"] for r in rows])) if not args.no_bm else None
     big = rows[-1]
     out = {
         "metric": "HSS compress+factor s/solve & Gentries/s, sym vs nonsym, at 1e-8 rel err",
@@ -538,7 +552,8 @@ def _run_kite(args):
                    "parallelism": "1 GPU"},
         "runs": rows,
         "mean_speedup_sym_vs_base": round(mean, 3),
-        "paper_context": "1.436 mean over 9 sizes on one 192-core CPU node (Table 4)",
+        "mean_speedup_bm_vs_base": round(mean_bm, 3) if mean_bm is not None else None,
+        "paper_context": "M-sym 1.436, BM 1.234 mean over 9 sizes on one 192-core CPU node (Table 4)",
     }
     print(json.dumps(out))
 
@@ -559,6 +574,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=300, help="predictor mode: training epochs")
     ap.add_argument("--n4", type=int, default=None, help="mixed mode: another N for the seven-arm star")
     ap.add_argument("--kite-max", type=int, default=None, help="kite sweep: largest DOF")
+    ap.add_argument("--no-bm", action="store_true", help="kite sweep: without the Burton-Miller column")
     ap.add_argument("--root-max", type=int, default=None,
                     help="largest dense top-level system (sum of ranks); default 2048, 8192 for --config 4")
     args = ap.parse_args()
@@ -632,6 +648,7 @@ def main():
                    "parallelism": "1 GPU"},
         "t_compress": round(st["t_compress"], 6),
         "t_compress_host": round(st["t_compress"] - st["t_compress_wait"], 6),
+        "host_seconds": {k: round(st["t_host_" + k], 6) for k in ("plan", "ids", "post", "factor")},
         "t_factor": round(st["t_factor"], 6),
         "t_solve": round(st["t_solve"], 6),
         "step_times": [round(v, 6) for v in per],

@@ -60,7 +60,17 @@ typedef enum {
   /* eq. naive_muller (unscaled), two-sided ID of M_R and M_L (the paper's Base) */
   SYMHSS_MULLER_BASE = 1,
   /* ablation: the symmetric matrix compressed two-sided, symmetry unused */
-  SYMHSS_MULLER_SYM_TWOSIDED = 2
+  SYMHSS_MULLER_SYM_TWOSIDED = 2,
+  /* eq. symmetric_pmchwt (row-scaled, exactly symmetric), one-sided ID.  Its
+     N_k0, N_k1 are hypersingular: the one-point rule converges at O(h) */
+  SYMHSS_PMCHWT_SYM = 3,
+  /* eq. naive_pmchwt (unscaled), two-sided ID */
+  SYMHSS_PMCHWT_BASE = 4,
+  /* eq. bm (Section 6.1, alpha = i/k0), unscaled, two-sided ID.  Unknowns in
+     the same [q; u] order as the other systems (the paper writes [u; q]);
+     rows: exterior equation minus alpha times its normal derivative, then
+     the interior equation; right-hand side [-(u_in + alpha q_in); 0] */
+  SYMHSS_BURTON_MILLER = 5
 } symhss_form;
 
 /* Materials: k_i = omega sqrt(eps_i) > 0 (Section 2); eps_i > 0. */
@@ -125,13 +135,16 @@ symhss_status symhss_factor(symhss_ctx *ctx);
 
 /* Solve A x = b for nrhs right-hand sides.  b and x are 2N x nrhs column-
  * major in the block order [q; u] and the scaling of the chosen form (row-
- * scaled for SYMHSS_MULLER_SYM*, unscaled for SYMHSS_MULLER_BASE).  Host
+ * scaled for SYMHSS_MULLER_SYM* and SYMHSS_PMCHWT_SYM, unscaled for the
+ * others).  Host
  * pointers unless flags has SYMHSS_DEVICE_PTRS.  b and x may not overlap. */
 symhss_status symhss_solve(symhss_ctx *ctx, const symhss_z *b, symhss_z *x, int32_t nrhs, int32_t flags);
 
 /* Right-hand side of the chosen form for the plane wave
  * u_in = exp(i k0 (cos a x1 + sin a x2)), q_in = du_in/dnu:
- * b = [-eps0 W u_in; W q_in] (eq. symmetric_muller) or [-eps0 u_in; q_in]. */
+ * b = [-eps0 W u_in; W q_in] (eq. symmetric_muller) or [-eps0 u_in; q_in];
+ * PMCHWT [-W u_in; W q_in / eps0] (W = I unscaled); Burton-Miller
+ * [-(u_in + alpha q_in); 0]. */
 symhss_status symhss_rhs_plane_wave(symhss_ctx *ctx, double angle, symhss_z *b, int32_t flags);
 
 /* Plane-wave right-hand sides of a batch: angles[t] for boundary t (the
@@ -305,6 +318,11 @@ typedef struct {
   double fp32_residual;      /* |b - A_HSS x| / |b| after the first FP32 solve */
   double refine_residual;    /* the same after the last one */
   double t_compress_wait;    /* of t_compress, seconds the host waited for the GPU */
+  /* host-side work of the last compress (seconds, wall clock, waits excluded) */
+  double t_host_plan;        /* active sets, proxy circles, near fields, next level's boxes */
+  double t_host_ids;         /* proxy points, index unions, kernel-block and ID descriptors */
+  double t_host_post;        /* skeletons, interpolation descriptors, child maps */
+  double t_host_factor;      /* queueing each level's factorisation (pipelined factor) */
 } symhss_stats;
 
 symhss_status symhss_get_stats(const symhss_ctx *ctx, symhss_stats *out);

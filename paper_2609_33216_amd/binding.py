@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsymhss.so")
 
 MULLER_SYM, MULLER_BASE, MULLER_SYM_TWOSIDED = 0, 1, 2
+PMCHWT_SYM, PMCHWT_BASE, BURTON_MILLER = 3, 4, 5
 DEVICE_PTRS = 1
 OPT_GRAPHS, OPT_AUTOTUNE, OPT_PERSISTENT, OPT_PREDICTOR, OPT_PROXY_MARGIN = 0, 1, 2, 3, 4
 OPT_PRECISION, OPT_REFINE_DIGITS, OPT_REFINE_MAXIT = 5, 6, 7
@@ -64,7 +65,9 @@ class Stats(ctypes.Structure):
                 ("proxy_bytes", ctypes.c_double), ("proxy_bytes_rule", ctypes.c_double),
                 ("refine_iters", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("fp32_residual", ctypes.c_double), ("refine_residual", ctypes.c_double),
-                ("t_compress_wait", ctypes.c_double)]
+                ("t_compress_wait", ctypes.c_double), ("t_host_plan", ctypes.c_double),
+                ("t_host_ids", ctypes.c_double), ("t_host_post", ctypes.c_double),
+                ("t_host_factor", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_

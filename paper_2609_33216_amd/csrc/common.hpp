@@ -107,8 +107,20 @@ struct MediumDev {
   double g0c, g1c;      // ln(k/2) + gamma for k0, k1
   double nd_re, nd_im;  // N_k0 - N_k1 diagonal without the -(Delta/4pi) ln(w/2pi) term
   double delta;         // k0^2 - k1^2
-  int row_scaled;       // 1: eq. symmetric_muller; 0: eq. naive_muller
+  int row_scaled;       // 1: rows scaled by w (eq. symmetric_muller / symmetric_pmchwt); 0: unscaled
+  int eq;               // kEqMuller, kEqPmchwt or kEqBurtonMiller
+  double ie0, ie1;      // 1 / eps0, 1 / eps1 (PMCHWT)
+  // individual (hypersingular) N_k diagonal without the point-dependent
+  // -pi/(6 w^2) + kappa^2/(24 pi) - (k^2/4pi) ln(w/2pi):
+  // i k^2/8 - (k^2/4pi)(ln(k/2) + gamma - 1/2)
+  double n0_re, n0_im, n1_re, n1_im;
+  double al_re, al_im;  // Burton-Miller coupling alpha = i / k0
 };
+
+// Which boundary integral system the entries belong to.
+constexpr int kEqMuller = 0;        // eq. symmetric_muller / naive_muller
+constexpr int kEqPmchwt = 1;        // eq. symmetric_pmchwt / naive_pmchwt
+constexpr int kEqBurtonMiller = 2;  // eq. bm, columns in [q; u] order
 
 // One block job of the kernel-block generator: the 2x2 Muller-like block
 // between row points and column points, written into a column-major matrix.

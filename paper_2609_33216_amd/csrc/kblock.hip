@@ -14,6 +14,19 @@
 // On the diagonal (o = s, a boundary node) the one-point corrected values
 // and the free terms -/+ (eps0 + eps1) w / 2 (or 1/2, unscaled) apply.
 //
+// The PMCHWT system (eq. symmetric_pmchwt / naive_pmchwt) combines the same
+// kernels with other weights and no free terms:
+//   A11 = -omega (eps0 G_k0 + eps1 G_k1),  A12 = omega (D_k0 + D_k1),
+//   A21 = omega (D*_k0 + D*_k1),           A22 = -omega (N_k0/eps0 + N_k1/eps1),
+// and the Burton-Miller system (eq. bm, alpha = i/k0, columns in [q; u]):
+//   A11 = -omega eps0 (G_k0 + alpha D*_k0) - alpha eps0 f,  A12 = omega (D_k0 + alpha N_k0) - f,
+//   A21 = -omega eps1 G_k1,                                 A22 = omega D_k1 + f,
+// f = w/2 (row-scaled) or 1/2 on the diagonal.  Both need the individual,
+// hypersingular N_k, whose one-point corrected diagonal is
+//   -pi/(6 w^2) + kappa^2/(24 pi) + i k^2/8 - (k^2/4pi)(ln(k/2) + gamma - 1/2 + ln(w/2pi))
+// (zeta(2) removes the trapezoidal rule's h^-1 term of the 1/t^2 part; the
+// rule then converges at first order, as Section 3.1 states for N_k).
+//
 // One thread evaluates one point pair and writes its (up to) four entries;
 // the Hankel functions of both wavenumbers are shared by the four.
 #include "kernels.hpp"
@@ -92,6 +105,128 @@ __device__ inline void muller_pair(const PointsDev& P, const MediumDev& md, int 
   }
 }
 
+// Hypersingular N_k diagonal: the k-independent part and the per-k part.
+__device__ inline double n_hyp_diag(double w, double kappa) {
+  return -kPi / (6.0 * w * w) + kappa * kappa * (1.0 / (24.0 * kPi));
+}
+
+__device__ inline void pmchwt_pair(const PointsDev& P, const MediumDev& md, int io, int is, cplx e[4]) {
+  const double e0 = md.eps0, e1 = md.eps1, i0 = md.ie0, i1 = md.ie1;
+  const double wo = P.w[io], ws = P.w[is];
+  const double om = md.row_scaled ? wo * ws : ws;
+  if (io == is && io < P.n_boundary) {
+    const double ell = log(wo * (0.5 / kPi));
+    const double g0r = -(md.g0c + ell) * (0.5 / kPi);
+    const double g1r = -(md.g1c + ell) * (0.5 / kPi);
+    e[0] = mk(-om * (e0 * g0r + e1 * g1r), -om * ((e0 + e1) * 0.25));
+    const double dd = -P.kappa[io] * (0.25 / kPi);
+    e[1] = mk(om * (dd + dd), 0.0);
+    e[2] = e[1];
+    const double hyp = n_hyp_diag(wo, P.kappa[io]);
+    const double n0r = hyp + md.n0_re - md.k0 * md.k0 * (0.25 / kPi) * ell;
+    const double n1r = hyp + md.n1_re - md.k1 * md.k1 * (0.25 / kPi) * ell;
+    e[3] = mk(-om * (i0 * n0r + i1 * n1r), -om * (i0 * md.n0_im + i1 * md.n1_im));
+    return;
+  }
+  const double dx = P.x[io] - P.x[is];
+  const double dy = P.y[io] - P.y[is];
+  const double r = sqrt(dx * dx + dy * dy);
+  const double invr = 1.0 / r;
+  const double dno = dx * P.nx[io] + dy * P.ny[io];
+  const double dns = dx * P.nx[is] + dy * P.ny[is];
+  const double nn = P.nx[io] * P.nx[is] + P.ny[io] * P.ny[is];
+  const JY01 a = jy01_call(md.k0 * r);
+  const JY01 b = jy01_call(md.k1 * r);
+  const double k0 = md.k0, k1 = md.k1;
+  const double pole = kTwoOverPi * invr;
+  {
+    const double sr = e0 * a.j0 + e1 * b.j0;
+    const double si = e0 * a.y0 + e1 * b.y0;
+    e[0] = mk(om * 0.25 * si, -om * 0.25 * sr);
+  }
+  {
+    const double dr_ = k0 * a.j1 + k1 * b.j1;
+    const double di_ = k0 * a.y1r + k1 * b.y1r - 2.0 * pole;
+    const double ire = -0.25 * di_, iim = 0.25 * dr_;
+    const double f12 = om * dns * invr;
+    const double f21 = -om * dno * invr;
+    e[1] = mk(ire * f12, iim * f12);
+    e[2] = mk(ire * f21, iim * f21);
+  }
+  {
+    const double h1r = i0 * k0 * a.j1 + i1 * k1 * b.j1;
+    const double h1i = i0 * k0 * a.y1r + i1 * k1 * b.y1r - (i0 + i1) * pole;
+    const double h0r = i0 * k0 * k0 * a.j0 + i1 * k1 * k1 * b.j0;
+    const double h0i = i0 * k0 * k0 * a.y0 + i1 * k1 * k1 * b.y0;
+    const double c = dno * dns;
+    const double invr2 = invr * invr;
+    const double f1 = nn * invr - 2.0 * c * invr2 * invr;
+    const double f0 = c * invr2;
+    const double sr = h1r * f1 + h0r * f0;
+    const double si = h1i * f1 + h0i * f0;
+    e[3] = mk(om * 0.25 * si, -om * 0.25 * sr);
+  }
+}
+
+// (i/4) (re + i im)
+__device__ inline cplx i4(double re, double im) { return mk(-0.25 * im, 0.25 * re); }
+
+__device__ inline void bm_pair(const PointsDev& P, const MediumDev& md, int io, int is, cplx e[4]) {
+  const double e0 = md.eps0, e1 = md.eps1;
+  const cplx al = mk(md.al_re, md.al_im);
+  const double wo = P.w[io], ws = P.w[is];
+  const double om = md.row_scaled ? wo * ws : ws;
+  if (io == is && io < P.n_boundary) {
+    const double ell = log(wo * (0.5 / kPi));
+    const cplx g0 = mk(-(md.g0c + ell) * (0.5 / kPi), 0.25);
+    const cplx g1 = mk(-(md.g1c + ell) * (0.5 / kPi), 0.25);
+    const double dd = -P.kappa[io] * (0.25 / kPi);
+    const cplx n0 = mk(n_hyp_diag(wo, P.kappa[io]) + md.n0_re - md.k0 * md.k0 * (0.25 / kPi) * ell, md.n0_im);
+    const double f = 0.5 * (md.row_scaled ? wo : 1.0);
+    e[0] = (-e0 * om) * (g0 + dd * al) - (e0 * f) * al;
+    e[1] = om * (mk(dd, 0.0) + al * n0) - mk(f, 0.0);
+    e[2] = (-e1 * om) * g1;
+    e[3] = mk(om * dd + f, 0.0);
+    return;
+  }
+  const double dx = P.x[io] - P.x[is];
+  const double dy = P.y[io] - P.y[is];
+  const double r = sqrt(dx * dx + dy * dy);
+  const double invr = 1.0 / r;
+  const double dno = dx * P.nx[io] + dy * P.ny[io];
+  const double dns = dx * P.nx[is] + dy * P.ny[is];
+  const double nn = P.nx[io] * P.nx[is] + P.ny[io] * P.ny[is];
+  const JY01 a = jy01_call(md.k0 * r);
+  const JY01 b = jy01_call(md.k1 * r);
+  const double k0 = md.k0, k1 = md.k1;
+  const double pole = kTwoOverPi * invr;
+  // k H1(k r) for both wavenumbers, k^2 H0(k0 r)
+  const double h1ar = k0 * a.j1, h1ai = k0 * a.y1r - pole;
+  const double h1br = k1 * b.j1, h1bi = k1 * b.y1r - pole;
+  const cplx G0 = i4(a.j0, a.y0);
+  const cplx G1 = i4(b.j0, b.y0);
+  const cplx Dy0 = (dns * invr) * i4(h1ar, h1ai);
+  const cplx Dx0 = (-dno * invr) * i4(h1ar, h1ai);
+  const cplx Dy1 = (dns * invr) * i4(h1br, h1bi);
+  const double c = dno * dns;
+  const double invr2 = invr * invr;
+  const double f1 = nn * invr - 2.0 * c * invr2 * invr;
+  const double f0 = c * invr2;
+  const cplx N0 = i4(h1ar * f1 + k0 * k0 * a.j0 * f0, h1ai * f1 + k0 * k0 * a.y0 * f0);
+  e[0] = (-e0 * om) * (G0 + al * Dx0);
+  e[1] = om * (Dy0 + al * N0);
+  e[2] = (-e1 * om) * G1;
+  e[3] = om * Dy1;
+}
+
+template <int EQ>
+__device__ inline void system_pair(const PointsDev& P, const MediumDev& md, int io, int is, cplx e[4]) {
+  if constexpr (EQ == kEqMuller) muller_pair(P, md, io, is, e);
+  else if constexpr (EQ == kEqPmchwt) pmchwt_pair(P, md, io, is, e);
+  else bm_pair(P, md, io, is, e);
+}
+
+template <int EQ>
 __global__ __launch_bounds__(256) void k_kblock(PointsDev P, const MediumDev* __restrict__ media,
                                                 const KJob* __restrict__ jobs,
                                                 const KTile* __restrict__ tiles,
@@ -116,7 +251,7 @@ __global__ __launch_bounds__(256) void k_kblock(PointsDev P, const MediumDev* __
     const int c1 = cmap1[J.coff + b];
     const int c2 = cmap2[J.coff + b];
     cplx e[4];
-    muller_pair(P, md, ra, cb, e);
+    system_pair<EQ>(P, md, ra, cb, e);
     if (J.mode != 2) {
       if (o1 >= 0 && c1 >= 0) J.out[o1 + ld * c1] = e[0];
       if (o1 >= 0 && c2 >= 0) J.out[o1 + ld * c2] = e[1];
@@ -152,7 +287,8 @@ __global__ void k_geometry(int n, const double* __restrict__ xin, const double* 
 }
 
 // Plane-wave right-hand side: u_in = exp(i k0 d.x), q_in = i k0 (d.nu) u_in;
-// b = [-eps0 W u_in; W q_in] (row-scaled) or [-eps0 u_in; q_in].
+// Muller-like b = [-eps0 W u_in; W q_in] (row-scaled) or [-eps0 u_in; q_in],
+// PMCHWT [-W u_in; W q_in / eps0], Burton-Miller [-(u_in + alpha q_in); 0].
 __global__ void k_rhs_plane(int n, PointsDev P, MediumDev md, double ca, double sa, cplx* b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -161,9 +297,18 @@ __global__ void k_rhs_plane(int n, PointsDev P, MediumDev md, double ca, double 
   sincos(ph, &s, &c);
   const double dn = md.k0 * (ca * P.nx[i] + sa * P.ny[i]);
   const double sc = md.row_scaled ? P.w[i] : 1.0;
-  b[i] = mk(-md.eps0 * sc * c, -md.eps0 * sc * s);
-  // i dn (c + i s) = (-dn s, dn c)
-  b[n + i] = mk(-sc * dn * s, sc * dn * c);
+  // q_in = i dn (c + i s) = (-dn s, dn c)
+  const cplx uin = mk(c, s), qin = mk(-dn * s, dn * c);
+  if (md.eq == kEqPmchwt) {
+    b[i] = (-sc) * uin;
+    b[n + i] = (sc * md.ie0) * qin;
+  } else if (md.eq == kEqBurtonMiller) {
+    b[i] = (-sc) * (uin + mk(md.al_re, md.al_im) * qin);
+    b[n + i] = mk(0.0, 0.0);
+  } else {
+    b[i] = mk(-md.eps0 * sc * c, -md.eps0 * sc * s);
+    b[n + i] = mk(-sc * dn * s, sc * dn * c);
+  }
 }
 
 __global__ void k_bessel(int n, const double* __restrict__ z, double* __restrict__ out) {
@@ -179,6 +324,7 @@ __global__ void k_bessel(int n, const double* __restrict__ z, double* __restrict
 
 // Direct FP64 product y = A x without storing A: one thread per row of the
 // 2N x 2N system, summing over all source nodes.
+template <int EQ>
 __global__ __launch_bounds__(256) void k_matvec_direct(PointsDev P, MediumDev md, const cplx* __restrict__ x,
                                                        cplx* __restrict__ y) {
   const int n = P.n_boundary;
@@ -187,7 +333,7 @@ __global__ __launch_bounds__(256) void k_matvec_direct(PointsDev P, MediumDev md
   cplx y1 = mk(0, 0), y2 = mk(0, 0);
   for (int j = 0; j < n; ++j) {
     cplx e[4];
-    muller_pair(P, md, i, j, e);
+    system_pair<EQ>(P, md, i, j, e);
     const cplx xq = x[j], xu = x[n + j];
     fma_acc(y1, e[0], xq);
     fma_acc(y1, e[1], xu);
@@ -198,12 +344,19 @@ __global__ __launch_bounds__(256) void k_matvec_direct(PointsDev P, MediumDev md
   y[n + i] = y2;
 }
 
-void launch_kblock(hipStream_t st, const PointsDev& P, const MediumDev* media, const KJob* jobs,
+void launch_kblock(hipStream_t st, int eq, const PointsDev& P, const MediumDev* media, const KJob* jobs,
                    const KTile* tiles, int ntiles, const int* rpt, const int* rmap1, const int* rmap2,
                    const int* cpt, const int* cmap1, const int* cmap2) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_kblock, dim3(ntiles), dim3(256), 0, st, P, media, jobs, tiles, rpt, rmap1, rmap2, cpt,
-                     cmap1, cmap2);
+  if (eq == kEqPmchwt)
+    hipLaunchKernelGGL(k_kblock<kEqPmchwt>, dim3(ntiles), dim3(256), 0, st, P, media, jobs, tiles, rpt, rmap1,
+                       rmap2, cpt, cmap1, cmap2);
+  else if (eq == kEqBurtonMiller)
+    hipLaunchKernelGGL(k_kblock<kEqBurtonMiller>, dim3(ntiles), dim3(256), 0, st, P, media, jobs, tiles, rpt,
+                       rmap1, rmap2, cpt, cmap1, cmap2);
+  else
+    hipLaunchKernelGGL(k_kblock<kEqMuller>, dim3(ntiles), dim3(256), 0, st, P, media, jobs, tiles, rpt, rmap1,
+                       rmap2, cpt, cmap1, cmap2);
   HIPCHK(hipGetLastError());
 }
 
@@ -226,7 +379,13 @@ void launch_bessel(hipStream_t st, int n, const double* z, double* out) {
 }
 
 void launch_matvec_direct(hipStream_t st, const PointsDev& P, const MediumDev& md, const cplx* x, cplx* y) {
-  hipLaunchKernelGGL(k_matvec_direct, dim3(cdiv_int(P.n_boundary, 256)), dim3(256), 0, st, P, md, x, y);
+  const dim3 g(cdiv_int(P.n_boundary, 256));
+  if (md.eq == kEqPmchwt)
+    hipLaunchKernelGGL(k_matvec_direct<kEqPmchwt>, g, dim3(256), 0, st, P, md, x, y);
+  else if (md.eq == kEqBurtonMiller)
+    hipLaunchKernelGGL(k_matvec_direct<kEqBurtonMiller>, g, dim3(256), 0, st, P, md, x, y);
+  else
+    hipLaunchKernelGGL(k_matvec_direct<kEqMuller>, g, dim3(256), 0, st, P, md, x, y);
   HIPCHK(hipGetLastError());
 }
 

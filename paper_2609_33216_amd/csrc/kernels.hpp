@@ -33,7 +33,7 @@ struct InterpDesc {
 
 // kernel-block generation (kblock.hip)
 // media: device array indexed by KJob::med
-void launch_kblock(hipStream_t st, const PointsDev& P, const MediumDev* media, const KJob* jobs,
+void launch_kblock(hipStream_t st, int eq, const PointsDev& P, const MediumDev* media, const KJob* jobs,
                    const KTile* tiles, int ntiles, const int* rpt, const int* rmap1, const int* rmap2,
                    const int* cpt, const int* cmap1, const int* cmap2);
 void launch_geometry(hipStream_t st, int n, const double* x, const double* dx, const double* ddx, double* px,

@@ -298,6 +298,7 @@ class Solver {
   DBuf<cplx> vec_;  // staging of b / x for host-pointer solves
   // execution options (symhss_configure)
   int use_graphs_ = 0, autotune_ = 0, persistent_ = -1;
+  int eq_ = kEqMuller;  // which system the entry generator evaluates
   bool capturing_ = false;
   uint64_t plan_sig_ = 0;     // structure produced by the last compress
   uint64_t assemble_gen_ = 0;

@@ -17,14 +17,19 @@ def make_solver(wl, form=0, leaf=None, tol=None, n_proxy=None, root_max=0):
     return s
 
 
-def oracle_system(wl, row_scaled=True):
+def oracle_system(wl, row_scaled=True, eq="muller"):
     x, dx, ddx = wl.boundary()
     g = geometry.discretize(x, dx, ddx)
     med = Medium(wl.k0, wl.k1, wl.eps0, wl.eps1)
-    A = kernels.assemble(g, med, row_scaled)
+    A = kernels.assemble(g, med, row_scaled, eq)
     uin, qin = dense.plane_wave(g, wl.k0, wl.angle)
-    b = dense.rhs(g, med, uin, qin, row_scaled)
+    b = dense.rhs(g, med, uin, qin, row_scaled, eq)
     return g, med, A, b
+
+
+# form of the C-ABI -> (system, row-scaled) of the oracle
+FORMS = {0: ("muller", True), 1: ("muller", False), 2: ("muller", True), 3: ("pmchwt", True),
+         4: ("pmchwt", False), 5: ("bm", False)}
 
 
 def rel(a, b):
