@@ -54,9 +54,9 @@ MI355X_HBM_TBS = 8.0
 MEASURED_TRAFFIC = {
     "k_cpqr": {"source": "cpqr.hip", "sha": "0b76eff22489f474", "bytes": 3.087e+09,
                "profile": "profiles/k_cpqr_star5-n32768.md"},
-    "k_lu_fused": {"source": "dense_body.inc", "sha": "e894b095366fc3e4", "bytes": 7.645e+08,
+    "k_lu_fused": {"source": "dense_body.inc", "sha": "592e2bdeb70f2822", "bytes": 7.431e+08,
                    "profile": "profiles/k_lu_fused_star5-n32768.md"},
-    "k_kblock": {"source": "kblock.hip", "sha": "8d35d53fffcbe977", "bytes": 7.427e+07,
+    "k_kblock": {"source": "kblock.hip", "sha": "840bcffe0b166028", "bytes": 7.428e+07,
                  "profile": "profiles/k_kblock_star5-n32768.md"},
 }
 
