@@ -69,7 +69,8 @@ class Uploader {
  private:
   struct Chunk {
     char* d;
-    char* h;
+    char* h;   // pinned staging
+    char* hd;  // the staging as the device addresses it
     size_t cap, used;
   };
   hipStream_t st_ = nullptr;
