@@ -5,6 +5,7 @@
 #include <chrono>
 #include <functional>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "bessel.hpp"
@@ -300,6 +301,8 @@ class Solver {
   // execution options (symhss_configure)
   int use_graphs_ = 0, autotune_ = 0, persistent_ = -1;
   int eq_ = kEqMuller;  // which system the entry generator evaluates
+  // cos / sin of 2 pi i / np, i < np, per proxy count np
+  std::unordered_map<int, std::vector<double>> unit_circle_;
   bool capturing_ = false;
   uint64_t plan_sig_ = 0;     // structure produced by the last compress
   uint64_t assemble_gen_ = 0;
