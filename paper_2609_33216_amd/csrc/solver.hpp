@@ -301,6 +301,7 @@ class Solver {
   // execution options (symhss_configure)
   int use_graphs_ = 0, autotune_ = 0, persistent_ = -1;
   int eq_ = kEqMuller;  // which system the entry generator evaluates
+  uint64_t unhashed_plans_ = 0;  // compresses run without the structure hash
   // cos / sin of 2 pi i / np, i < np, per proxy count np
   std::unordered_map<int, std::vector<double>> unit_circle_;
   bool capturing_ = false;
