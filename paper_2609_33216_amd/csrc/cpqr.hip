@@ -3,13 +3,14 @@
 // two-sided baseline of each half of M_L^T).
 //
 // For M (m x n, column-major, in place): M P = Q R.  Pivot j is the remaining
-// column of largest trailing norm (lowest index on ties); trailing norms are
+// column of largest trailing norm (lowest position on ties); trailing norms are
 // recomputed exactly while each column is updated, so no downdating error
 // accumulates.  The rank k is the first j with |R_jj| <= tol |R_00|
 // (tolerance mode) or a fixed target (resume mode, used to equalise row and
 // column ranks in the two-sided baseline).  Afterwards (want_T) T = R11^{-1}
 // R12 overwrites R12, so that M[:, P[k:]] ~= M[:, P[:k]] T; a pass that may
-// be resumed leaves R12 in place.
+// be resumed leaves R12 in place.  Columns are not moved: column t of R (or
+// T) is stored in the memory of original column perm[t].
 //
 // One workgroup per matrix.  The Householder vector of the current step is
 // staged in LDS; every wavefront then takes groups of trailing columns,
@@ -32,26 +33,27 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Apply the step's reflector H = I - tau v v^H to CB consecutive columns
-// c0 .. c0+CB-1 (those < n) over rows j..m-1 and recompute their norms below
-// row j.  The column segments (R*64 rows per column) are loaded into
+// Apply the step's reflector H = I - tau v v^H to the nc <= CB columns
+// pc[0..nc) (physical indices) over rows j..m-1 and recompute their norms
+// below row j.  The column segments (R*64 rows per column) are loaded into
 // registers together, so one wavefront keeps CB*R loads in flight.
 template <int R, int CB>
-__device__ inline void reflect_columns(const IdDesc& D, int j, int c0, const cplx* __restrict__ vj, double tau,
-                                       double* vn, int lane) {
-  const int m = D.m, n = D.n;
+__device__ inline void reflect_columns(const IdDesc& D, int j, const int* pc, int nc, const cplx* __restrict__ vj,
+                                       double tau, double* vn, int lane) {
   const long ld = D.ld;
-  const int rows = m - j;
+  const int rows = D.m - j;
   cplx a[CB][R];
   cplx w[CB];
+  int c[CB];
+#pragma unroll
+  for (int b = 0; b < CB; ++b) c[b] = b < nc ? pc[b] : -1;
 #pragma unroll
   for (int b = 0; b < CB; ++b) {
-    const int c = c0 + b;
-    const cplx* col = D.A + ld * (c < n ? c : 0) + j;
+    const cplx* col = D.A + ld * (c[b] >= 0 ? c[b] : 0) + j;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int i = lane + 64 * q;
-      a[b][q] = (c < n && i < rows) ? col[i] : mk(0, 0);
+      a[b][q] = (c[b] >= 0 && i < rows) ? col[i] : mk(0, 0);
     }
   }
 #pragma unroll
@@ -74,14 +76,13 @@ __device__ inline void reflect_columns(const IdDesc& D, int j, int c0, const cpl
   double s[CB];
 #pragma unroll
   for (int b = 0; b < CB; ++b) {
-    const int c = c0 + b;
     const cplx tw = tau * w[b];
-    cplx* col = D.A + ld * (c < n ? c : 0) + j;
+    cplx* col = D.A + ld * (c[b] >= 0 ? c[b] : 0) + j;
     s[b] = 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int i = lane + 64 * q;
-      if (c < n && i < rows) {
+      if (c[b] >= 0 && i < rows) {
         const cplx vi = vj[i];
         a[b][q].re -= vi.re * tw.re - vi.im * tw.im;
         a[b][q].im -= vi.re * tw.im + vi.im * tw.re;
@@ -98,11 +99,12 @@ __device__ inline void reflect_columns(const IdDesc& D, int j, int c0, const cpl
   if (lane == 0) {
 #pragma unroll
     for (int b = 0; b < CB; ++b)
-      if (c0 + b < n) vn[c0 + b] = s[b];
+      if (c[b] >= 0) vn[c[b]] = s[b];
   }
 }
 
-// One column, any number of rows (streamed from global memory).
+// One column (physical index c), any number of rows (streamed from global
+// memory).
 __device__ inline void reflect_column_long(const IdDesc& D, int j, int c, const cplx* __restrict__ vj, double tau,
                                            double* vn, int lane) {
   const int rows = D.m - j;
@@ -126,34 +128,38 @@ __device__ inline void reflect_column_long(const IdDesc& D, int j, int c, const 
 }
 
 // The ID of one matrix by one workgroup of NT threads.
+//
+// Column interchanges are logical: columns stay where they are in memory and
+// pos[t] (in LDS, copied to D.perm at the end) names the column at position
+// t, so column t of the factored matrix - R, or T after want_T - lives at
+// A[:, perm[t]].  A resumed pass starts from the stored perm.  The pivot
+// choice is made by every thread from the per-wavefront candidates, which
+// leaves two workgroup barriers per step.
 template <int NT, int R, int CB>
 __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
   const int m = D.m, n = D.n;
   const long ld = D.ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int nwaves = NT / 64;
-  // LDS: vn[n] doubles, v[m] complex, reduction scratch
+  // LDS: vn[n] doubles (by physical column), v[m] complex, reduction
+  // scratch, pos[n] ints
   double* vn = lds;
   cplx* v = reinterpret_cast<cplx*>(lds + n);
-  double* red = lds + n + 2 * m;           // nwaves doubles
+  double* red = lds + n + 2 * m;                     // nwaves doubles
   int* redi = reinterpret_cast<int*>(red + nwaves);  // nwaves ints
-  __shared__ int s_piv;
-  __shared__ int s_stop;
+  int* pos = redi + nwaves;                          // n ints
   __shared__ double s_tau;
 
   const int kmax = m < n ? m : n;
-  int j0 = (D.target >= 0) ? *D.rank : 0;
-  if (j0 == 0) {
-    for (int c = tid; c < n; c += NT) D.perm[c] = c;
-  }
+  const int j0 = (D.target >= 0) ? *D.rank : 0;
+  for (int c = tid; c < n; c += NT) pos[c] = (j0 == 0) ? c : D.perm[c];
   __syncthreads();
-  // trailing norms over rows j0..m-1
-  for (int c = wave; c < n; c += nwaves) {
+  // trailing norms over rows j0..m-1 of the columns not yet pivoted
+  for (int t = j0 + wave; t < n; t += nwaves) {
+    const int c = pos[t];
+    const cplx* col = D.A + ld * c;
     double s = 0.0;
-    if (c >= j0) {
-      const cplx* col = D.A + ld * c;
-      for (int i = j0 + lane; i < m; i += 64) s += abs2(col[i]);
-    }
+    for (int i = j0 + lane; i < m; i += 64) s += abs2(col[i]);
     s = wave_sum(s);
     if (lane == 0) vn[c] = s;
   }
@@ -161,12 +167,12 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
   double r00 = (j0 > 0) ? *D.r00 : 0.0;
   int j = j0;
   for (; j < kmax; ++j) {
-    // pivot: argmax vn[c], c >= j, lowest index on ties
+    // pivot: the position t >= j of largest trailing norm, lowest t on ties
     double best = -1.0;
     int bi = n;
-    for (int c = j + tid; c < n; c += NT) {
-      const double x = vn[c];
-      if (x > best) { best = x; bi = c; }
+    for (int t = j + tid; t < n; t += NT) {
+      const double x = vn[pos[t]];
+      if (x > best) { best = x; bi = t; }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -176,110 +182,84 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
     }
     if (lane == 0) { red[wave] = best; redi[wave] = bi; }
     __syncthreads();
-    if (tid == 0) {
-      double b = red[0];
-      int ix = redi[0];
-      for (int w = 1; w < nwaves; ++w) {
-        if (red[w] > b || (red[w] == b && redi[w] < ix)) { b = red[w]; ix = redi[w]; }
-      }
-      const double nrm = sqrt(b > 0.0 ? b : 0.0);
-      int stop = 0;
-      if (j == 0) r00 = nrm;
-      if (D.target >= 0) {
-        stop = (j >= D.target);
-      } else {
-        stop = !(r00 > 0.0) || !(nrm > tol * r00);  // NaN-safe
-      }
-      if (ix >= n) stop = 1;  // no admissible pivot (non-finite norms)
-      if (j == 0) *D.r00 = r00;
-      s_stop = stop;
-      s_piv = ix;
-    }
-    __syncthreads();
-    if (s_stop) break;
-    const int p = s_piv;
-    if (p != j) {
-      cplx* cj = D.A + ld * j;
-      cplx* cp = D.A + ld * p;
-      for (int i = tid; i < m; i += NT) {
-        const cplx t = cj[i];
-        cj[i] = cp[i];
-        cp[i] = t;
-      }
-      if (tid == 0) {
-        const int t = D.perm[j];
-        D.perm[j] = D.perm[p];
-        D.perm[p] = t;
-        const double tv = vn[j];
-        vn[j] = vn[p];
-        vn[p] = tv;
-      }
-    }
-    __syncthreads();
+    double b = red[0];
+    int p = redi[0];
+#pragma unroll
+    for (int w = 1; w < nwaves; ++w)
+      if (red[w] > b || (red[w] == b && redi[w] < p)) { b = red[w]; p = redi[w]; }
+    const double nrm = sqrt(b > 0.0 ? b : 0.0);
+    if (j == 0) r00 = nrm;
+    int stop;
+    if (D.target >= 0) stop = (j >= D.target);
+    else stop = !(r00 > 0.0) || !(nrm > tol * r00);  // NaN-safe
+    if (p >= n) stop = 1;  // no admissible pivot (non-finite norms)
+    if (j == 0 && tid == 0) *D.r00 = r00;
+    if (stop) break;  // uniform: every thread decided from the same slots
     // Householder reflector H = I - tau v v^H with v_0 = 1 mapping the pivot
     // column's trailing part y = [alpha; x] to beta e_1, beta = -e^{i arg alpha} |y|.
-    cplx* cj = D.A + ld * j;
     if (wave == 0) {
+      const int cp = pos[p];
+      cplx* cj = D.A + ld * cp;
       double s = 0.0;
       for (int i = j + 1 + lane; i < m; i += 64) s += abs2(cj[i]);
       s = wave_sum(s);
       const cplx alpha = cj[j];
       const double aa = sqrt(abs2(alpha));
-      const double nrm = sqrt(aa * aa + s);
+      const double nr = sqrt(aa * aa + s);
       cplx beta, u0;
       double tau;
-      if (nrm == 0.0) {
+      if (nr == 0.0) {
         beta = mk(0, 0);
         u0 = mk(1, 0);
         tau = 0.0;
       } else {
         const cplx ph = aa > 0.0 ? mk(alpha.re / aa, alpha.im / aa) : mk(1, 0);
-        beta = mk(-ph.re * nrm, -ph.im * nrm);
+        beta = mk(-ph.re * nr, -ph.im * nr);
         u0 = alpha - beta;
         const double u0a = abs2(u0);
         tau = 2.0 / (1.0 + s / u0a);
       }
-      for (int i = j + 1 + lane; i < m; i += 64) {
-        const cplx vi = cdiv(cj[i], u0);
-        v[i] = vi;
-        cj[i] = vi;
-      }
+      for (int i = j + 1 + lane; i < m; i += 64) v[i] = cdiv(cj[i], u0);
       if (lane == 0) {
         v[j] = mk(1, 0);
         cj[j] = beta;
         s_tau = tau;
+        pos[p] = pos[j];
+        pos[j] = cp;
       }
     }
     __syncthreads();
     const double tau = s_tau;
-    // apply to the trailing columns, CB at a time per wavefront
+    // apply to the columns at positions j+1..n-1, CB at a time per wavefront
     const int rows = m - j;
     if (rows <= R * 64) {
-      for (int c0 = j + 1 + CB * wave; c0 < n; c0 += CB * nwaves) reflect_columns<R, CB>(D, j, c0, v + j, tau, vn, lane);
+      for (int t0 = j + 1 + CB * wave; t0 < n; t0 += CB * nwaves)
+        reflect_columns<R, CB>(D, j, pos + t0, min(CB, n - t0), v + j, tau, vn, lane);
     } else {
-      for (int c = j + 1 + wave; c < n; c += nwaves) reflect_column_long(D, j, c, v + j, tau, vn, lane);
+      for (int t = j + 1 + wave; t < n; t += nwaves) reflect_column_long(D, j, pos[t], v + j, tau, vn, lane);
     }
     __syncthreads();
   }
   const int k = j;
+  for (int c = tid; c < n; c += NT) D.perm[c] = pos[c];
   if (tid == 0) *D.rank = k;
-  __syncthreads();
   if (want_T) {
     // T = R11^{-1} R12 in place, one column per thread
-    for (int c = k + tid; c < n; c += NT) {
-      cplx* col = D.A + ld * c;
+    for (int t = k + tid; t < n; t += NT) {
+      cplx* col = D.A + ld * pos[t];
       for (int i = k - 1; i >= 0; --i) {
         cplx s = col[i];
         for (int l = i + 1; l < k; ++l) {
-          const cplx r = D.A[i + ld * l];
+          const cplx r = D.A[i + ld * pos[l]];
           const cplx x = col[l];
           s.re -= r.re * x.re - r.im * x.im;
           s.im -= r.re * x.im + r.im * x.re;
         }
-        col[i] = cdiv(s, D.A[i + ld * i]);
+        col[i] = cdiv(s, D.A[i + ld * pos[i]]);
       }
     }
   }
+  __syncthreads();
 }
 
 // One workgroup per matrix (queue == nullptr), or a persistent grid whose
@@ -319,7 +299,7 @@ __global__ void k_build_interp(const InterpDesc* __restrict__ descs) {
     const long idx = D.transpose ? (D.col0 + pc) + ldo * (D.row0 + c) : (D.row0 + c) + ldo * (D.col0 + pc);
     D.out[idx] = mk(1, 0);
   } else {
-    const cplx* tc = D.A + (long)D.ld * c;
+    const cplx* tc = D.A + (long)D.ld * pc;  // column c of T stays in place at perm[c]
     for (int r = 0; r < D.k; ++r) {
       const long idx = D.transpose ? (D.col0 + pc) + ldo * (D.row0 + r) : (D.row0 + r) + ldo * (D.col0 + pc);
       D.out[idx] = tc[r];
@@ -342,7 +322,8 @@ __global__ void k_equalise_ranks(int npairs, const int* __restrict__ ia, const i
 }
 
 size_t cpqr_lds_bytes(int mmax, int nmax) {
-  return sizeof(double) * (size_t)nmax + sizeof(cplx) * (size_t)mmax + 16 * (sizeof(double) + sizeof(int)) + 64;
+  return sizeof(double) * (size_t)nmax + sizeof(cplx) * (size_t)mmax + 16 * (sizeof(double) + sizeof(int)) +
+         sizeof(int) * (size_t)nmax + 64;
 }
 
 // Variants: 256 threads (4 wavefronts, several workgroups per CU; CB = 4

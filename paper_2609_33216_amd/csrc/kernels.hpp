@@ -22,7 +22,7 @@ struct IdDesc {
 // transposed placement out[col0 + perm[c], row0 + r] for a row ID (L = R^T;
 // plain transpose, no conjugate).  The output must be zeroed beforehand.
 struct InterpDesc {
-  const cplx* A;  // T lives in A[0:k, k:n]
+  const cplx* A;  // column c >= k of T lives in A[0:k, perm[c]]
   int ld, k, n;
   const int* perm;
   cplx* out;
