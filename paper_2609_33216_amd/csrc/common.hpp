@@ -143,6 +143,49 @@ struct KTile {
   int job, r0, c0, pad;
 };
 
+// Arg-max over the 64 lanes of a wavefront: the largest v (NaN never wins),
+// the lowest i among equal v; every lane receives the result.  Within each
+// 16-lane row the pairs are exchanged by DPP lane permutations (quad
+// exchanges by 1 and 2, then the half-row and row mirrors: after each step
+// every lane holds the result over the lanes combined so far); the four row
+// results are then read with readlane and combined in the same order on
+// every lane.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp_step(double& v, int& i) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+  const double ov = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  argmax_dpp_step<0xB1>(v, i);   // quad_perm [1, 0, 3, 2]
+  argmax_dpp_step<0x4E>(v, i);   // quad_perm [2, 3, 0, 1]
+  argmax_dpp_step<0x141>(v, i);  // row_half_mirror
+  argmax_dpp_step<0x140>(v, i);  // row_mirror
+  const long long b = __double_as_longlong(v);
+  double bv = 0.0;
+  int bi = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int lo = __builtin_amdgcn_readlane((int)b, 16 * r);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * r);
+    const int ri = __builtin_amdgcn_readlane(i, 16 * r);
+    const double rv = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    if (r == 0 || rv > bv || (rv == bv && ri < bi)) {
+      bv = rv;
+      bi = ri;
+    }
+  }
+  v = bv;
+  i = bi;
+}
+
 inline void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) {
     throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));

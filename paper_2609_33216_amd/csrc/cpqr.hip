@@ -174,12 +174,7 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
       const double x = vn[pos[t]];
       if (x > best) { best = x; bi = t; }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
+    wave_argmax(best, bi);
     if (lane == 0) { red[wave] = best; redi[wave] = bi; }
     __syncthreads();
     double b = red[0];
