@@ -27,11 +27,7 @@ __global__ void k_zero_i32(int* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+__device__ inline double wave_sum(double v) { return wave_sum_dpp(v); }
 
 // Apply the step's reflector H = I - tau v v^H to the nc <= CB columns
 // pc[0..nc) (physical indices) over rows j..m-1 and recompute their norms
@@ -66,12 +62,9 @@ __device__ inline void reflect_columns(const IdDesc& D, int j, const int* pc, in
     }
   }
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-    for (int b = 0; b < CB; ++b) {
-      w[b].re += __shfl_xor(w[b].re, off, 64);
-      w[b].im += __shfl_xor(w[b].im, off, 64);
-    }
+  for (int b = 0; b < CB; ++b) {
+    w[b].re = wave_sum_dpp(w[b].re);
+    w[b].im = wave_sum_dpp(w[b].im);
   }
   double s[CB];
 #pragma unroll
@@ -92,10 +85,7 @@ __device__ inline void reflect_columns(const IdDesc& D, int j, const int* pc, in
     }
   }
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-    for (int b = 0; b < CB; ++b) s[b] += __shfl_xor(s[b], off, 64);
-  }
+  for (int b = 0; b < CB; ++b) s[b] = wave_sum_dpp(s[b]);
   if (lane == 0) {
 #pragma unroll
     for (int b = 0; b < CB; ++b)
