@@ -204,6 +204,11 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+__device__ __forceinline__ float readlane_real(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double readlane_real(double v, int lane) { return readlane_f64(v, lane); }
+
 __device__ __forceinline__ double wave_sum_dpp(double v) {
   v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
   v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
