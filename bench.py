@@ -52,9 +52,9 @@ MI355X_HBM_TBS = 8.0
 # on a plain 512 MiB copy (fetch x2.0, write x1.0).  Valid only while the
 # kernel's source is the one profiled: keyed by the SHA-256 prefix of its file.
 MEASURED_TRAFFIC = {
-    "k_cpqr": {"source": "cpqr.hip", "sha": "58be99f95fea400d", "bytes": 2.990e+09,
+    "k_cpqr": {"source": "cpqr.hip", "sha": "7e2412fc039566bb", "bytes": 3.002e+09,
                "profile": "profiles/k_cpqr_star5-n32768.md"},
-    "k_lu_fused": {"source": "dense_body.inc", "sha": "987bfe5305885f7a", "bytes": 7.701e+08,
+    "k_lu_fused": {"source": "dense_body.inc", "sha": "987bfe5305885f7a", "bytes": 7.706e+08,
                    "profile": "profiles/k_lu_fused_star5-n32768.md"},
     "k_kblock": {"source": "kblock.hip", "sha": "840bcffe0b166028", "bytes": 7.431e+07,
                  "profile": "profiles/k_kblock_star5-n32768.md"},

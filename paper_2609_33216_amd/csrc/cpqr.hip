@@ -229,18 +229,29 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
   for (int c = tid; c < n; c += NT) D.perm[c] = pos[c];
   if (tid == 0) *D.rank = k;
   if (want_T) {
-    // T = R11^{-1} R12 in place, one column per thread
+    // T = R11^{-1} R12 in place, one column per thread; the row sums are
+    // unrolled so that their independent loads are in flight together
     for (int t = k + tid; t < n; t += NT) {
       cplx* col = D.A + ld * pos[t];
       for (int i = k - 1; i >= 0; --i) {
-        cplx s = col[i];
-        for (int l = i + 1; l < k; ++l) {
+        cplx s = col[i], s2 = mk(0, 0);
+        int l = i + 1;
+#pragma unroll 4
+        for (; l + 1 < k; l += 2) {
+          const cplx r = D.A[i + ld * pos[l]], r2 = D.A[i + ld * pos[l + 1]];
+          const cplx x = col[l], x2 = col[l + 1];
+          s.re -= r.re * x.re - r.im * x.im;
+          s.im -= r.re * x.im + r.im * x.re;
+          s2.re -= r2.re * x2.re - r2.im * x2.im;
+          s2.im -= r2.re * x2.im + r2.im * x2.re;
+        }
+        if (l < k) {
           const cplx r = D.A[i + ld * pos[l]];
           const cplx x = col[l];
           s.re -= r.re * x.re - r.im * x.im;
           s.im -= r.re * x.im + r.im * x.re;
         }
-        col[i] = cdiv(s, D.A[i + ld * pos[i]]);
+        col[i] = cdiv(s + s2, D.A[i + ld * pos[i]]);
       }
     }
   }
