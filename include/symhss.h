@@ -51,7 +51,9 @@ typedef enum {
   SYMHSS_EDEVICE = 3,   /* HIP runtime error */
   SYMHSS_ESTATE = 4,    /* call out of order */
   SYMHSS_ESINGULAR = 5, /* zero pivot in a diagonal-block LU */
-  SYMHSS_ERANK = 6      /* proxy matrix beyond the ID kernel's limits */
+  SYMHSS_ERANK = 6,     /* proxy matrix beyond the ID kernel's limits */
+  SYMHSS_ENOTCONV = 7   /* mixed-precision refinement reached its iteration limit above its
+                           target; the outputs hold the last iterate */
 } symhss_status;
 
 typedef enum {
@@ -124,13 +126,16 @@ symhss_status symhss_assemble_batch(symhss_ctx *ctx, int32_t count, const int64_
 
 /* Proxy-method compression (Section 4.1), levels L..1: generates M_R (and
  * M_L for the two-sided forms) on the GPU and computes the column-pivoted
- * QR IDs of their halves. */
+ * QR IDs of their halves.  A compress that fails leaves the context
+ * assembled only (factor and solve return SYMHSS_ESTATE until a compress
+ * succeeds). */
 symhss_status symhss_compress(symhss_ctx *ctx);
 
 /* Compressed-equation factorisation (Section 4.2): per box LU of the
  * diagonal block D, X = D^{-1} L, A~ = (R X)^{-1}; parent blocks
  * [[A~_c1, S_c1c2], [S_c2c1, A~_c2]]; dense LU at the root.  ESINGULAR on a
- * zero pivot. */
+ * zero pivot.  A factor that fails leaves the context compressed (solve
+ * returns SYMHSS_ESTATE until a factor succeeds). */
 symhss_status symhss_factor(symhss_ctx *ctx);
 
 /* Solve A x = b for nrhs right-hand sides.  b and x are 2N x nrhs column-
@@ -139,6 +144,25 @@ symhss_status symhss_factor(symhss_ctx *ctx);
  * others).  Host
  * pointers unless flags has SYMHSS_DEVICE_PTRS.  b and x may not overlap. */
 symhss_status symhss_solve(symhss_ctx *ctx, const symhss_z *b, symhss_z *x, int32_t nrhs, int32_t flags);
+
+/* Physical interface (Section 2, the transmission conditions that close the
+ * exterior and interior problems): from the incident field's boundary data
+ * u_in and q_in = du_in/dnu at the nodes, solve the chosen form's system and
+ * return the boundary traces q and u of the solution (the unknowns [q; u]).
+ * The result does not depend on the form beyond its discretisation error.
+ * uin, qin, q, u: N x nrhs column-major (N = all nodes of a batch, boundary t
+ * at rows [B_t, B_t + N_t)); host pointers unless flags has
+ * SYMHSS_DEVICE_PTRS.  Inputs and outputs may not overlap.  ESTATE before
+ * factor; ENOTCONV as for symhss_solve. */
+symhss_status symhss_solve_incident(symhss_ctx *ctx, const symhss_z *uin, const symhss_z *qin, symhss_z *q,
+                                    symhss_z *u, int32_t nrhs, int32_t flags);
+
+/* Incident plane wave at the nodes: u_in = exp(i k0 (cos a x1 + sin a x2)) and
+ * q_in = du_in/dnu, with a = angles[t] on boundary t (one angle for a single
+ * boundary); uin, qin: N values each (host pointers unless
+ * SYMHSS_DEVICE_PTRS).  Valid after assemble. */
+symhss_status symhss_plane_wave(symhss_ctx *ctx, const double *angles, symhss_z *uin, symhss_z *qin,
+                                int32_t flags);
 
 /* Right-hand side of the chosen form for the plane wave
  * u_in = exp(i k0 (cos a x1 + sin a x2)), q_in = du_in/dnu:
@@ -192,7 +216,10 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
  *       until |r| / |b| <= 10^-digits (every right-hand side) or the
  *       iteration limit.  Changing it requires a new symhss_factor.
  *  SYMHSS_OPT_REFINE_DIGITS [10] the refinement target 10^-digits (1..15).
- *  SYMHSS_OPT_REFINE_MAXIT  [10] the refinement iteration limit (1..100).
+ *  SYMHSS_OPT_REFINE_MAXIT  [10] the refinement iteration limit (1..100).  A
+ *       solve whose residual is still above the target after the last
+ *       iteration (or not finite) returns SYMHSS_ENOTCONV with x holding the
+ *       last iterate.
  *  SYMHSS_OPT_RANK_LEAF    [0] k_L > 0: fixed-rank schedule (Section 4.3):
  *       every ID of a box at level l of its boundary's tree (leaves at level
  *       L) has rank min(round(k_L a^(L - l)), columns, rows) per half, instead
@@ -216,6 +243,13 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
 #define SYMHSS_OPT_RANK_LEAF 8
 #define SYMHSS_OPT_RANK_SCALE 9
 #define SYMHSS_OPT_PIPELINE 10
+/*  SYMHSS_OPT_DEVICE_LIMIT [0] bytes of device memory the context's work
+ *       buffers may hold (0: no limit).  A call that would allocate beyond it
+ *       fails with SYMHSS_ENOMEM; a compress or factor that fails leaves the
+ *       context assembled (resp. compressed), so that later stages return
+ *       SYMHSS_ESTATE until it is run again.  Small staging chunks for launch
+ *       descriptors are not counted. */
+#define SYMHSS_OPT_DEVICE_LIMIT 11
 symhss_status symhss_configure(symhss_ctx *ctx, int32_t option, int64_t value);
 
 /* Rank predictor (sizes fixed before the factorisation runs, Section 4.3):

@@ -44,7 +44,7 @@ import numpy as np
 import scipy.linalg
 
 from .geometry import Geometry
-from .kernels import Medium, PointSet, muller_blocks
+from .kernels import Medium, PointSet, system_blocks
 from .idec import column_id, interp_matrix
 
 
@@ -88,14 +88,21 @@ class Box:
 
 
 class ReferenceHSS:
+    """eq selects the system ("muller", "pmchwt" or "bm", as in kernels.system_blocks);
+    only the row-scaled Muller-like and PMCHWT systems are symmetric.  rank fixes
+    every ID's rank; schedule = (k_L, a) gives a box at level l the rank
+    round(k_L a^(L - l)) (Section 4.3) instead of the tolerance rule."""
+
     def __init__(self, geom: Geometry, med: Medium, leaf: int, tol: float,
                  two_sided: bool = False, row_scaled: bool = True,
-                 n_proxy_min: int = 64, proxy_ratio: float = 1.5, rank: int | None = None):
-        if not row_scaled and not two_sided:
-            raise ValueError("the unscaled system is not symmetric: use two_sided=True")
-        self.g, self.med = geom, med
+                 n_proxy_min: int = 64, proxy_ratio: float = 1.5, rank: int | None = None,
+                 eq: str = "muller", schedule: tuple | None = None):
+        if not two_sided and (not row_scaled or eq == "bm"):
+            raise ValueError("a non-symmetric system needs two_sided=True")
+        self.g, self.med, self.eq = geom, med, eq
         self.tol, self.two_sided, self.row_scaled = tol, two_sided, row_scaled
         self.n_proxy_min, self.ratio, self.fixed_rank = n_proxy_min, proxy_ratio, rank
+        self.schedule = schedule
         self.ranges = tree_ranges(geom.n, leaf)
         self.L = len(self.ranges) - 1
         self.boxes = []
@@ -125,7 +132,7 @@ class ReferenceHSS:
                     continue
                 o = PointSet.boundary(g, obs_pts[e])
                 s = PointSet.boundary(g, src_pts[t])
-                B = muller_blocks(o, s, self.med, self.row_scaled)[2 * e + t]
+                B = system_blocks(o, s, self.med, self.row_scaled, self.eq)[2 * e + t]
                 self.entries_generated += B.size
                 blk.append(B)
             out_rows.append(np.hstack(blk) if blk else np.zeros((len(obs_pts[e]), 0)))
@@ -142,11 +149,11 @@ class ReferenceHSS:
             s = PointSet.boundary(self.g, cols[t])
             parts = []
             for e in range(2):
-                parts.append(muller_blocks(prox, s, self.med, self.row_scaled)[2 * e + t])
+                parts.append(system_blocks(prox, s, self.med, self.row_scaled, self.eq)[2 * e + t])
             for e in range(2):
                 if len(near[e]):
                     o = PointSet.boundary(self.g, near[e])
-                    parts.append(muller_blocks(o, s, self.med, self.row_scaled)[2 * e + t])
+                    parts.append(system_blocks(o, s, self.med, self.row_scaled, self.eq)[2 * e + t])
             M = np.vstack(parts)
             self.entries_generated += M.size
             halves.append(M)
@@ -163,11 +170,11 @@ class ReferenceHSS:
             o = PointSet.boundary(self.g, rows[e])
             parts = []
             for t in range(2):
-                parts.append(muller_blocks(o, prox, self.med, self.row_scaled)[2 * e + t])
+                parts.append(system_blocks(o, prox, self.med, self.row_scaled, self.eq)[2 * e + t])
             for t in range(2):
                 if len(near[t]):
                     s = PointSet.boundary(self.g, near[t])
-                    parts.append(muller_blocks(o, s, self.med, self.row_scaled)[2 * e + t])
+                    parts.append(system_blocks(o, s, self.med, self.row_scaled, self.eq)[2 * e + t])
             M = np.hstack(parts)
             self.entries_generated += M.size
             halves.append(M.T)
@@ -201,12 +208,16 @@ class ReferenceHSS:
                     c1, c2 = self.boxes[lev + 1][2 * bi], self.boxes[lev + 1][2 * bi + 1]
                     box.rows = [np.concatenate([c1.rskel[h], c2.rskel[h]]) for h in range(2)]
                     box.cols = [np.concatenate([c1.cskel[h], c2.cskel[h]]) for h in range(2)]
+            rank = self.fixed_rank
+            if self.schedule is not None:
+                kL, a = self.schedule
+                rank = int(round(kL * a ** (self.L - lev)))
             for box in self.boxes[lev]:
                 MR = self._proxy_rows(box, box.cols)
-                cid = [column_id(MR[h], self.tol, self.fixed_rank) for h in range(2)]
+                cid = [column_id(MR[h], self.tol, rank) for h in range(2)]
                 if self.two_sided:
                     MLt = self._proxy_cols_T(box, box.rows)
-                    rid = [column_id(MLt[h], self.tol, self.fixed_rank) for h in range(2)]
+                    rid = [column_id(MLt[h], self.tol, rank) for h in range(2)]
                     ks = [max(cid[h][0], rid[h][0]) for h in range(2)]
                     cid = [column_id(MR[h], self.tol, ks[h]) if ks[h] != cid[h][0] else cid[h]
                            for h in range(2)]

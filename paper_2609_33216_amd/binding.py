@@ -20,10 +20,11 @@ PMCHWT_SYM, PMCHWT_BASE, BURTON_MILLER = 3, 4, 5
 DEVICE_PTRS = 1
 OPT_GRAPHS, OPT_AUTOTUNE, OPT_PERSISTENT, OPT_PREDICTOR, OPT_PROXY_MARGIN = 0, 1, 2, 3, 4
 OPT_PRECISION, OPT_REFINE_DIGITS, OPT_REFINE_MAXIT = 5, 6, 7
-OPT_RANK_LEAF, OPT_RANK_SCALE, OPT_PIPELINE = 8, 9, 10
+OPT_RANK_LEAF, OPT_RANK_SCALE, OPT_PIPELINE, OPT_DEVICE_LIMIT = 8, 9, 10, 11
 
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ESINGULAR, ERANK, ENOTCONV = range(8)
 _STATUS = {
-    0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ESINGULAR", 6: "ERANK",
+    0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ESINGULAR", 6: "ERANK", 7: "ENOTCONV",
 }
 
 
@@ -86,7 +87,8 @@ EXPORTS = [
     "symhss_eval_bessel", "symhss_matvec_direct", "symhss_get_stats", "symhss_box_query",
     "symhss_assemble_batch", "symhss_rhs_plane_wave_batch", "symhss_configure",
     "symhss_predictor_train", "symhss_predictor_load", "symhss_predictor_get", "symhss_predictor_predict",
-    "symhss_predictor_grad", "symhss_box_table", "symhss_hss_matvec",
+    "symhss_predictor_grad", "symhss_box_table", "symhss_hss_matvec", "symhss_solve_incident",
+    "symhss_plane_wave",
 ]
 
 PREDICTOR_WEIGHTS = 8845
@@ -142,6 +144,8 @@ def load(path: str | None = None):
         "symhss_predictor_grad": ([vp, vp, vp, vp, i64, ctypes.c_float, vp, vp], ctypes.c_int),
         "symhss_box_table": ([vp, ctypes.POINTER(i64), vp, vp, vp], ctypes.c_int),
         "symhss_hss_matvec": ([vp, vp, vp, i32], ctypes.c_int),
+        "symhss_solve_incident": ([vp, vp, vp, vp, vp, i32, i32], ctypes.c_int),
+        "symhss_plane_wave": ([vp, vp, vp, vp, i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -194,12 +198,13 @@ class Solver:
     def configure(self, graphs: bool | None = None, autotune: bool | None = None, persistent: int | None = None,
                   predictor: bool | None = None, proxy_margin: int | None = None, mixed: bool | None = None,
                   refine_digits: int | None = None, refine_maxit: int | None = None,
-                  rank_leaf: int | None = None, rank_scale: float | None = None, pipeline: bool | None = None):
+                  rank_leaf: int | None = None, rank_scale: float | None = None, pipeline: bool | None = None,
+                  device_limit: int | None = None):
         """Execution options (see symhss_configure); rank_scale is the growth a (e.g. 1.15)."""
         for opt, v in ((OPT_GRAPHS, graphs), (OPT_AUTOTUNE, autotune), (OPT_PERSISTENT, persistent),
                        (OPT_PREDICTOR, predictor), (OPT_PROXY_MARGIN, proxy_margin), (OPT_PRECISION, mixed),
                        (OPT_REFINE_DIGITS, refine_digits), (OPT_REFINE_MAXIT, refine_maxit),
-                       (OPT_RANK_LEAF, rank_leaf), (OPT_PIPELINE, pipeline),
+                       (OPT_RANK_LEAF, rank_leaf), (OPT_PIPELINE, pipeline), (OPT_DEVICE_LIMIT, device_limit),
                        (OPT_RANK_SCALE, None if rank_scale is None else round(1000 * rank_scale))):
             if v is not None:
                 self._check(self.lib.symhss_configure(self.h, opt, int(v)))
@@ -322,6 +327,30 @@ class Solver:
         """Device-resident solve: b_ptr, x_ptr are HBM addresses of 2N x nrhs complex128."""
         self._check(self.lib.symhss_solve(self.h, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), nrhs,
                                           DEVICE_PTRS))
+
+    def solve_incident(self, uin, qin):
+        """Traces (q, u) of the solution for incident data u_in, q_in = du_in/dnu at
+        the nodes: (N,) or (N, nrhs) complex host arrays."""
+        uin = np.asarray(uin, dtype=np.complex128)
+        qin = np.asarray(qin, dtype=np.complex128)
+        one = uin.ndim == 1
+        U = np.asfortranarray(uin.reshape(uin.shape[0], -1))
+        Q = np.asfortranarray(qin.reshape(qin.shape[0], -1))
+        if U.shape != Q.shape or U.shape[0] != self.n:
+            raise ValueError("u_in and q_in must both have N rows and the same columns")
+        q = np.zeros_like(U, order="F")
+        u = np.zeros_like(U, order="F")
+        self._check(self.lib.symhss_solve_incident(self.h, _ptr(U), _ptr(Q), _ptr(q), _ptr(u), U.shape[1], 0))
+        return (q[:, 0].copy(), u[:, 0].copy()) if one else (q, u)
+
+    def plane_wave(self, angle):
+        """(u_in, q_in) of the plane wave at the nodes; angle: one value, or one per boundary."""
+        nt = len(getattr(self, "batch_n", [])) or 1
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(angle, dtype=np.float64), (nt,)))
+        uin = np.zeros(self.n, dtype=np.complex128)
+        qin = np.zeros(self.n, dtype=np.complex128)
+        self._check(self.lib.symhss_plane_wave(self.h, _ptr(a), _ptr(uin), _ptr(qin), 0))
+        return uin, qin
 
     def rhs_plane_wave(self, angle: float):
         b = np.zeros(2 * self.n, dtype=np.complex128)

@@ -20,6 +20,7 @@ thread_local std::string g_create_error;
 template <class F>
 symhss_status guarded(symhss_ctx* ctx, F&& f) {
   if (!ctx || !ctx->s) return SYMHSS_EINVAL;
+  symhss::BudgetScope budget(ctx->s->budget());
   try {
     f(*ctx->s);
     ctx->err.clear();
@@ -37,6 +38,9 @@ symhss_status guarded(symhss_ctx* ctx, F&& f) {
   } catch (const std::range_error& e) {
     ctx->err = e.what();
     return SYMHSS_ERANK;
+  } catch (const symhss::NotConverged& e) {
+    ctx->err = e.what();
+    return SYMHSS_ENOTCONV;
   } catch (const std::exception& e) {
     ctx->err = e.what();
     return SYMHSS_EDEVICE;
@@ -109,6 +113,16 @@ symhss_status symhss_factor(symhss_ctx* ctx) {
 
 symhss_status symhss_solve(symhss_ctx* ctx, const symhss_z* b, symhss_z* x, int32_t nrhs, int32_t flags) {
   return guarded(ctx, [&](symhss::Solver& s) { s.solve(b, x, nrhs, flags); });
+}
+
+symhss_status symhss_solve_incident(symhss_ctx* ctx, const symhss_z* uin, const symhss_z* qin, symhss_z* q,
+                                    symhss_z* u, int32_t nrhs, int32_t flags) {
+  return guarded(ctx, [&](symhss::Solver& s) { s.solve_incident(uin, qin, q, u, nrhs, flags); });
+}
+
+symhss_status symhss_plane_wave(symhss_ctx* ctx, const double* angles, symhss_z* uin, symhss_z* qin,
+                                int32_t flags) {
+  return guarded(ctx, [&](symhss::Solver& s) { s.plane_wave_incident(angles, uin, qin, flags); });
 }
 
 symhss_status symhss_rhs_plane_wave(symhss_ctx* ctx, double angle, symhss_z* b, int32_t flags) {

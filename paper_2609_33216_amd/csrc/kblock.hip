@@ -289,26 +289,66 @@ __global__ void k_geometry(int n, const double* __restrict__ xin, const double* 
 // Plane-wave right-hand side: u_in = exp(i k0 d.x), q_in = i k0 (d.nu) u_in;
 // Muller-like b = [-eps0 W u_in; W q_in] (row-scaled) or [-eps0 u_in; q_in],
 // PMCHWT [-W u_in; W q_in / eps0], Burton-Miller [-(u_in + alpha q_in); 0].
-__global__ void k_rhs_plane(int n, PointsDev P, MediumDev md, double ca, double sa, cplx* b) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Right-hand side rows of node i from the incident trace u_in and its normal
+// derivative q_in (eq. symmetric_muller / naive_muller, naive_pmchwt, bm);
+// sc = w_i for the row-scaled systems, 1 otherwise.
+__device__ inline void incident_rhs(const MediumDev& md, double sc, cplx uin, cplx qin, cplx& b1, cplx& b2) {
+  if (md.eq == kEqPmchwt) {
+    b1 = (-sc) * uin;
+    b2 = (sc * md.ie0) * qin;
+  } else if (md.eq == kEqBurtonMiller) {
+    b1 = (-sc) * (uin + mk(md.al_re, md.al_im) * qin);
+    b2 = mk(0.0, 0.0);
+  } else {
+    b1 = (-md.eps0 * sc) * uin;
+    b2 = sc * qin;
+  }
+}
+
+// u_in = exp(i k0 d.x), q_in = i k0 (d.nu) u_in at node i.
+__device__ inline void plane_wave_at(const PointsDev& P, const MediumDev& md, double ca, double sa, int i,
+                                     cplx& uin, cplx& qin) {
   const double ph = md.k0 * (ca * P.x[i] + sa * P.y[i]);
   double s, c;
   sincos(ph, &s, &c);
   const double dn = md.k0 * (ca * P.nx[i] + sa * P.ny[i]);
-  const double sc = md.row_scaled ? P.w[i] : 1.0;
-  // q_in = i dn (c + i s) = (-dn s, dn c)
-  const cplx uin = mk(c, s), qin = mk(-dn * s, dn * c);
-  if (md.eq == kEqPmchwt) {
-    b[i] = (-sc) * uin;
-    b[n + i] = (sc * md.ie0) * qin;
-  } else if (md.eq == kEqBurtonMiller) {
-    b[i] = (-sc) * (uin + mk(md.al_re, md.al_im) * qin);
-    b[n + i] = mk(0.0, 0.0);
-  } else {
-    b[i] = mk(-md.eps0 * sc * c, -md.eps0 * sc * s);
-    b[n + i] = mk(-sc * dn * s, sc * dn * c);
-  }
+  uin = mk(c, s);
+  qin = mk(-dn * s, dn * c);
+}
+
+__global__ void k_rhs_plane(int n, PointsDev P, MediumDev md, double ca, double sa, cplx* b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cplx uin, qin;
+  plane_wave_at(P, md, ca, sa, i, uin, qin);
+  incident_rhs(md, md.row_scaled ? P.w[i] : 1.0, uin, qin, b[i], b[n + i]);
+}
+
+__global__ void k_plane_incident(int n, PointsDev P, MediumDev md, double ca, double sa, cplx* uin, cplx* qin) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  plane_wave_at(P, md, ca, sa, i, uin[i], qin[i]);
+}
+
+// Column c of the right-hand sides: b[c ldb + (i, n + i)] from the traces
+// uin[c ldi + i], qin[c ldi + i].
+__global__ void k_rhs_incident(int n, PointsDev P, MediumDev md, const cplx* __restrict__ uin,
+                               const cplx* __restrict__ qin, int ldi, cplx* __restrict__ b, int ldb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t c = blockIdx.y;
+  cplx* bc = b + c * ldb;
+  incident_rhs(md, md.row_scaled ? P.w[i] : 1.0, uin[c * ldi + i], qin[c * ldi + i], bc[i], bc[n + i]);
+}
+
+// Unknowns [q; u] of one boundary (column c at x + c ldx) -> the traces q, u.
+__global__ void k_split_traces(int n, const cplx* __restrict__ x, int ldx, cplx* __restrict__ q,
+                               cplx* __restrict__ u, int ldo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t c = blockIdx.y;
+  q[c * ldo + i] = x[c * ldx + i];
+  u[c * ldo + i] = x[c * ldx + n + i];
 }
 
 __global__ void k_bessel(int n, const double* __restrict__ z, double* __restrict__ out) {
@@ -369,6 +409,25 @@ void launch_geometry(hipStream_t st, int n, const double* x, const double* dx, c
 
 void launch_rhs_plane(hipStream_t st, int n, const PointsDev& P, const MediumDev& md, double angle, cplx* b) {
   hipLaunchKernelGGL(k_rhs_plane, dim3(cdiv_int(n, 256)), dim3(256), 0, st, n, P, md, cos(angle), sin(angle), b);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_plane_incident(hipStream_t st, int n, const PointsDev& P, const MediumDev& md, double angle, cplx* uin,
+                           cplx* qin) {
+  hipLaunchKernelGGL(k_plane_incident, dim3(cdiv_int(n, 256)), dim3(256), 0, st, n, P, md, cos(angle), sin(angle),
+                     uin, qin);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_rhs_incident(hipStream_t st, int n, const PointsDev& P, const MediumDev& md, const cplx* uin,
+                         const cplx* qin, int ldi, cplx* b, int ldb, int nrhs) {
+  hipLaunchKernelGGL(k_rhs_incident, dim3(cdiv_int(n, 256), nrhs), dim3(256), 0, st, n, P, md, uin, qin, ldi, b,
+                     ldb);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_split_traces(hipStream_t st, int n, const cplx* x, int ldx, cplx* q, cplx* u, int ldo, int nrhs) {
+  hipLaunchKernelGGL(k_split_traces, dim3(cdiv_int(n, 256), nrhs), dim3(256), 0, st, n, x, ldx, q, u, ldo);
   HIPCHK(hipGetLastError());
 }
 

@@ -39,6 +39,14 @@ void launch_kblock(hipStream_t st, int eq, const PointsDev& P, const MediumDev* 
 void launch_geometry(hipStream_t st, int n, const double* x, const double* dx, const double* ddx, double* px,
                      double* py, double* nx, double* ny, double* w, double* kappa);
 void launch_rhs_plane(hipStream_t st, int n, const PointsDev& P, const MediumDev& md, double angle, cplx* b);
+// u_in and q_in = du_in/dnu of the plane wave at the n nodes of P
+void launch_plane_incident(hipStream_t st, int n, const PointsDev& P, const MediumDev& md, double angle, cplx* uin,
+                           cplx* qin);
+// right-hand sides of md's system from nrhs columns of traces (leading dimension ldi) into b (ldb)
+void launch_rhs_incident(hipStream_t st, int n, const PointsDev& P, const MediumDev& md, const cplx* uin,
+                         const cplx* qin, int ldi, cplx* b, int ldb, int nrhs);
+// solution columns [q; u] of one boundary (ldx) -> traces q and u (ldo)
+void launch_split_traces(hipStream_t st, int n, const cplx* x, int ldx, cplx* q, cplx* u, int ldo, int nrhs);
 void launch_bessel(hipStream_t st, int n, const double* z, double* out);
 void launch_matvec_direct(hipStream_t st, const PointsDev& P, const MediumDev& md, const cplx* x, cplx* y);
 

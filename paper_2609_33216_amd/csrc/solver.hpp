@@ -2,6 +2,7 @@
 // lists and the per-level launch sequence of compress, factor and solve.
 #pragma once
 
+#include <algorithm>
 #include <chrono>
 #include <functional>
 #include <string>
@@ -15,34 +16,73 @@
 
 namespace symhss {
 
-// Device allocation owned by the context.
+// Device memory of one context: the bytes its work buffers hold, and an
+// optional limit (0: none) beyond which an allocation fails as if the device
+// were full.  A call into a context makes its budget the thread's current one.
+struct DeviceBudget {
+  size_t used = 0, limit = 0;
+};
+inline thread_local DeviceBudget* tl_budget = nullptr;
+struct BudgetScope {
+  DeviceBudget* prev;
+  explicit BudgetScope(DeviceBudget* b) : prev(tl_budget) { tl_budget = b; }
+  ~BudgetScope() { tl_budget = prev; }
+};
+
+// A refinement that ended at its iteration limit above its target (the
+// iterate is still returned).
+struct NotConverged : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+// Device allocation owned by the context (charged to the budget current when
+// it was made).
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  DeviceBudget* charged = nullptr;
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), charged(o.charged) {
+    o.p = nullptr;
+    o.n = 0;
+    o.charged = nullptr;
+  }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      charged = o.charged;
+      o.p = nullptr;
+      o.n = 0;
+      o.charged = nullptr;
+    }
     return *this;
   }
   ~DBuf() { release(); }
   void release() {
     if (p) (void)hipFree(p);
+    if (charged) charged->used -= std::min(charged->used, n * sizeof(T));
     p = nullptr;
     n = 0;
+    charged = nullptr;
   }
   void ensure(size_t m) {
     if (m <= n) return;
     release();
     if (m == 0) return;
+    DeviceBudget* b = tl_budget;
+    if (b && b->limit && b->used + m * sizeof(T) > b->limit) throw std::bad_alloc();
     if (hipMalloc(&p, m * sizeof(T)) != hipSuccess) {
       p = nullptr;
       throw std::bad_alloc();
     }
     n = m;
+    charged = b;
+    if (b) b->used += m * sizeof(T);
   }
   size_t bytes() const { return n * sizeof(T); }
 };
@@ -170,6 +210,8 @@ class Solver {
   void compress();
   void factor();
   void solve(const symhss_z* b, symhss_z* x, int nrhs, int flags);
+  void solve_incident(const symhss_z* uin, const symhss_z* qin, symhss_z* q, symhss_z* u, int nrhs, int flags);
+  void plane_wave_incident(const double* angles, symhss_z* uin, symhss_z* qin, int flags);
   void rhs_plane_wave(double angle, symhss_z* b, int flags);
   void rhs_plane_wave_batch(const double* angles, symhss_z* b, int flags);
   void eval_entries(int64_t nr, const int64_t* rows, int64_t nc, const int64_t* cols, symhss_z* out);
@@ -186,10 +228,14 @@ class Solver {
     return s;
   }
   hipStream_t stream() const { return st_; }
+  DeviceBudget* budget() { return &budget_; }
 
   int stage = 0;  // 0 none, 1 assembled, 2 compressed, 3 factored
 
  private:
+  // declared before every device buffer it is charged with, so that it is
+  // destroyed after them
+  DeviceBudget budget_;
   // planning
   void build_tree();
   void set_active(int h);
@@ -200,6 +246,7 @@ class Solver {
     return hev_[h - 1].boxes[hev_[h - 1].tstart[B.tree] + 2 * B.li + w];
   }
   // compress pieces
+  void compress_impl();
   void compress_level(int h);
   // one generation + ID pass over some boxes of a height
   struct IdPass {
@@ -217,6 +264,7 @@ class Solver {
   void proxy_ids(int h, const std::vector<int>& which, IdPass& P);
   void box_features_of(int h, const Box& B, float* f) const;
   // factor pieces
+  void factor_impl();
   void factor_layout();
   void factor_layout_level(int h);
   void factor_layout_root();
@@ -226,10 +274,14 @@ class Solver {
   void factor_enqueue();
   uint64_t plan_signature() const;
   // launches with a choice of variant (autotuned per size bucket when enabled)
-  void run_cpqr(const IdDesc* d, int count, int mmax, int nmax, int want_T, cplx* data, size_t data_elems);
+  void run_cpqr(const IdDesc* d, int count, int mmax, int nmax, int want_T, cplx* data, size_t data_elems, int* ints,
+                size_t nints, double* dbl, size_t ndbl);
   void run_lu(const LuDesc* d, int count, int nmax, int ncolmax, int nrhsmax, cplx* data, size_t data_elems,
               int* info, int ninfo, double flops);
   void solve_enqueue(const cplx* db, cplx* dx, int nrhs);
+  // the solve of device vectors (graph replay, mixed-precision refinement);
+  // false if a refinement stopped at its iteration limit above its target
+  bool solve_device(const cplx* db, cplx* dx, int nrhs, int flags);
   struct Sweep64;
   struct Sweep32;
   template <class S>
@@ -238,7 +290,7 @@ class Solver {
   void factor_level_mixed(int h);
   void factor_root_mixed();
   void hss_matvec_enqueue(const cplx* x, cplx* y);
-  void solve_mixed(const cplx* db, cplx* dx, int nrhs);
+  bool solve_mixed(const cplx* db, cplx* dx, int nrhs);
   void ensure_sweep_buffers(int nrhs, bool fp32);
   // kernel-block launches
   struct KBatch {
@@ -298,6 +350,7 @@ class Solver {
   DBuf<f32::cplx> rworkf_;
   DBuf<double> norms_;
   DBuf<cplx> vec_;  // staging of b / x for host-pointer solves
+  DBuf<cplx> inc_;  // incident data, right-hand sides and solutions of solve_incident
   // execution options (symhss_configure)
   int use_graphs_ = 0, autotune_ = 0, persistent_ = -1;
   int eq_ = kEqMuller;  // which system the entry generator evaluates
@@ -322,6 +375,8 @@ class Solver {
   std::vector<std::pair<uint64_t, int>> tuned_;
   int tuned_choice(uint64_t key) const;
   DBuf<cplx> tune_backup_;
+  DBuf<int> tune_backup_int_;
+  DBuf<double> tune_backup_dbl_;
   DBuf<cplx> tune_backup_lu_;  // LU trials run on the factor stream
   DBuf<int> queue_;
   std::vector<TimerPair> timers_;

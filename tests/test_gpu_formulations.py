@@ -8,11 +8,13 @@
 * HSS solutions (one-sided ID for the symmetric PMCHWT, two-sided for the
   unscaled PMCHWT and Burton-Miller) against the oracle's dense LU solution
   of the same system within 1e-8 at a ragged size (N = 1600, leaf 128); with
-  the paper's fixed-rank schedule on the kite within 1e-7 (fixed ranks do not
-  control the error).
+  the paper's fixed-rank schedule on the kite within 3x of the oracle's own
+  HSS error at that schedule (fixed ranks do not control the error; the
+  oracle's values are stored in tests/golden/kite_fixed_rank_oracle.txt).
 """
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -70,23 +72,42 @@ def test_solve_vs_dense(form):
     assert e < 1e-8
 
 
+def _oracle_fixed_rank_error(form):
+    """The oracle's own HSS error on the kite at the same fixed-rank schedule
+    (tests/golden/kite_fixed_rank_oracle.txt, written by
+    tests/golden/make_kite_fixed_rank.py from oracle.hss only)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kite_fixed_rank_oracle.txt")
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        f, _, _, _, e = line.split()
+        if int(f) == form:
+            return float(e)
+    raise KeyError(form)
+
+
+@pytest.mark.parametrize("root_max", [0, -1])
 @pytest.mark.parametrize("form", [3, 4, 5])
-def test_kite_fixed_rank_vs_dense(form):
+def test_kite_fixed_rank_vs_dense(form, root_max):
+    # Fixed ranks do not control the error, and the hypersingular N_k of these
+    # systems (condition number O(N)) amplifies the truncation of the paper's
+    # schedule: the oracle's own HSS solver at the same schedule lands
+    # 2.8e-7 .. 6.2e-7 from the dense solution (against 2.0e-8 for the
+    # Muller-like system).  The GPU must stay within 3x of that.  root_max -1
+    # compresses every level down to two boxes as the oracle does; the default
+    # stops at the first level whose ranks fit the dense top-level system.
     wl = workloads.Workload("kite-n1600", "kite", (), 1600, 2.0, 2.0 * math.sqrt(3.0), 0.0, leaf=128)
     eq, rs = FORMS[form]
     _, _, A, b = oracle_system(wl, rs, eq)
-    s = make_solver(wl, form=form)
+    s = make_solver(wl, form=form, root_max=root_max)
     s.configure(rank_leaf=30, rank_scale=1.15)
     s.compress()
     s.factor()
     x = s.solve(b)
     e = rel(x, dense.solve_dense(A, b))
-    print("kite form", form, "error vs dense", e)
-    # fixed ranks do not control the error: the truncation of the paper's
-    # schedule is amplified by the hypersingular N_k (condition number O(N)),
-    # 1e-8 to 1e-7 here, far below these systems' O(h) discretisation error
-    # (about 1e-2 at this N)
-    assert e < 1e-7
+    ref = _oracle_fixed_rank_error(form)
+    print("kite form", form, "root_max", root_max, "error vs dense", e, "oracle HSS at the same schedule", ref)
+    assert e <= 3 * ref
 
 
 def test_symmetric_pmchwt_generates_fewer_entries():

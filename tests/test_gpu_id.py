@@ -15,6 +15,8 @@ Pivot indices are not compared: ties and rounding may pick other, equally
 valid skeletons.
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -51,18 +53,34 @@ def _proxy_matrix(s, g, med, level, box):
     return halves, cols
 
 
-@pytest.mark.parametrize("wl_name", ["circle", "star"])
+# circle, star: the 1024-thread ID variants (fewer than 128 half matrices per
+# launch); star128: 128 leaves, so 256 half matrices per launch at the lowest
+# levels, which take the 256-thread variant; bigproxy: 320 proxy points per
+# circle, so that proxy matrices have more than 512 rows and are reflected by
+# the streamed long-column path.
+@pytest.mark.parametrize("wl_name", ["circle", "star", "star128", "bigproxy"])
 def test_id_bounds(wl_name):
     if wl_name == "circle":
         wl = workloads.scaled_config(workloads.config1(), 1024, leaf=64)
-    else:
+    elif wl_name == "star":
         wl = workloads.config2_reduced(2048)
+    elif wl_name == "star128":
+        wl = workloads.scaled_config(workloads.config2(), 8192, leaf=64)
+    else:
+        wl = dataclasses.replace(workloads.config2_reduced(2048), n_proxy=320)
     tol = wl.tol
     s, g, med = _setup(wl)
     st = s.stats()
     L = st["levels"]
     n = g.n
-    for level in sorted({L, max(L - 2, 1), max(st["root_level"], 1)}):
+    if wl_name == "bigproxy":
+        cx, cy, Rp, npx = s.box_query(L, 0, 10)
+        assert 2 * npx > 512
+    levels = {L, max(L - 2, 1), max(st["root_level"], 1)}
+    if wl_name == "star128":
+        levels = {L, L - 1}  # 128 and 64 boxes: 256 and 128 half matrices
+        assert 1 << L == 128
+    for level in sorted(levels):
         for box in (0, (1 << level) // 3):
             halves, cols = _proxy_matrix(s, g, med, level, box)
             R, Lm = s.box_interp(level, box)

@@ -64,3 +64,13 @@ def test_multiple_rhs():
     wl = workloads.scaled_config(workloads.config1(), 1024, leaf=64)
     err, _ = _run(wl, 0, nrhs=3)
     assert err < 1e-8
+
+
+def test_star_proxy_matrices_over_512_rows():
+    # 320 proxy points per circle: every proxy matrix has more than 512 rows,
+    # so the ID reflects its columns by the streamed long-column path
+    import dataclasses
+    wl = dataclasses.replace(workloads.config2_reduced(2048), n_proxy=320)
+    err, st = _run(wl, 0)
+    assert max(st["proxy_max"]) >= 320
+    assert err < 1e-8
