@@ -291,6 +291,21 @@ symhss_status symhss_predictor_load(symhss_ctx *ctx, const float *weights, int64
 symhss_status symhss_predictor_get(symhss_ctx *ctx, float *weights, int64_t count);
 /* rank_out[s] = exp(network(feat[s])) for n samples (host memory). */
 symhss_status symhss_predictor_predict(symhss_ctx *ctx, const float *feat, int64_t n, float *rank_out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): symhss_predictor_predict with device
+ * pointers (feat: n x 6 floats, rank_out: n floats, both in HBM), queued on
+ * the context's stream and returning without waiting for it.  The network's
+ * activations live in a fixed scratch array in the library's device memory
+ * (SYMHSS_PREDICT_NOALLOC_MAX samples, about 6.5 MB per device, held until
+ * the process ends); nothing is allocated, copied to the host or
+ * synchronised.  EINVAL for n < 0 or n > SYMHSS_PREDICT_NOALLOC_MAX; n = 0 does
+ * nothing.  Features are not checked: a non-finite feature gives a
+ * non-finite rank.  Every context on a device shares that device's scratch:
+ * calls that overlap on one GPU (other streams, other contexts, other host
+ * threads) race and must be ordered by the caller. */
+#define SYMHSS_PREDICT_NOALLOC_MAX 8192
+symhss_status symhss_predictor_predict_noalloc(symhss_ctx *ctx, const float *feat, int64_t n, float *rank_out);
 /* Training data after compress: for every compressed box (heights from the
  * leaves up, boundaries in order within a height) its 6 predictor features
  * (feat, count x 6), its measured rank, the larger of its halves' ranks

@@ -88,10 +88,11 @@ EXPORTS = [
     "symhss_assemble_batch", "symhss_rhs_plane_wave_batch", "symhss_configure",
     "symhss_predictor_train", "symhss_predictor_load", "symhss_predictor_get", "symhss_predictor_predict",
     "symhss_predictor_grad", "symhss_box_table", "symhss_hss_matvec", "symhss_solve_incident",
-    "symhss_plane_wave",
+    "symhss_plane_wave", "symhss_predictor_predict_noalloc",
 ]
 
 PREDICTOR_WEIGHTS = 8845
+PREDICT_NOALLOC_MAX = 8192
 N_FEATURES = 6
 
 
@@ -146,6 +147,7 @@ def load(path: str | None = None):
         "symhss_hss_matvec": ([vp, vp, vp, i32], ctypes.c_int),
         "symhss_solve_incident": ([vp, vp, vp, vp, vp, i32, i32], ctypes.c_int),
         "symhss_plane_wave": ([vp, vp, vp, vp, i32], ctypes.c_int),
+        "symhss_predictor_predict_noalloc": ([vp, vp, i64, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -235,6 +237,12 @@ class Solver:
         out = np.zeros(feat.shape[0], dtype=np.float32)
         self._check(self.lib.symhss_predictor_predict(self.h, _ptr(feat), feat.shape[0], _ptr(out)))
         return out
+
+    def predictor_predict_noalloc(self, feat_ptr: int, n: int, rank_ptr: int):
+        """Device-pointer inference (n x 6 float features -> n float ranks), queued
+        on the context's stream without allocating or waiting."""
+        self._check(self.lib.symhss_predictor_predict_noalloc(self.h, ctypes.c_void_p(feat_ptr), n,
+                                                              ctypes.c_void_p(rank_ptr)))
 
     def predictor_grad(self, w, feat, rank, alpha):
         w = np.ascontiguousarray(w, dtype=np.float32)

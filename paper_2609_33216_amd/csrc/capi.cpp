@@ -195,6 +195,12 @@ symhss_status symhss_predictor_predict(symhss_ctx* ctx, const float* feat, int64
   });
 }
 
+symhss_status symhss_predictor_predict_noalloc(symhss_ctx* ctx, const float* feat, int64_t n, float* rank_out) {
+  return guarded(ctx, [&](symhss::Solver& s) {
+    s.predictor().predict_device(s.stream(), feat, n, rank_out, s.infer_scratch());
+  });
+}
+
 symhss_status symhss_predictor_grad(symhss_ctx* ctx, const float* weights, const float* feat, const float* rank,
                                     int64_t n, float alpha, float* grad, float* loss) {
   return guarded(ctx, [&](symhss::Solver& s) {

@@ -11,6 +11,7 @@
 // vector: W1 (64 x 6, row-major), b1, W2 (64 x 64), b2, W3, b3, W4 (1 x 64), b4.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <random>
 
 #include "mlp.hpp"
@@ -116,7 +117,52 @@ __global__ void k_gather(const float* __restrict__ x, const float* __restrict__ 
 
 inline int blocks(long n) { return (int)((n + 255) / 256); }
 
+struct FeatureNorm {
+  double mu[kMlpFeatures], sd[kMlpFeatures];
+};
+
+// x[s, f] = (feat[s, f] - mu_f) / sd_f, formed in FP64 and rounded once (as
+// the host-side normalisation).
+__global__ void k_normalise(const float* __restrict__ feat, int n, FeatureNorm nm, float* __restrict__ x) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * kMlpFeatures) return;
+  const int f = e % kMlpFeatures;
+  x[e] = (float)(((double)feat[e] - nm.mu[f]) / nm.sd[f]);
+}
+
+// rank[s] = exp(y[s]) in FP64, rounded once.
+__global__ void k_exp_rank(const float* __restrict__ y, int n, float* __restrict__ rank) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) rank[s] = (float)exp((double)y[s]);
+}
+
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[64] = {nullptr};
+
 }  // namespace
+
+// Allocation-free inference: per sample the normalised input, the three
+// hidden layers and the output, for at most kMlpNoAllocSamples samples
+// (6.5 MB).  Each device holds one copy, shared by every context on it.  Host
+// code never uses this name as an address: kernels get the pointer that
+// mlp_scratch_address looked up for the device.
+constexpr int kInferFloats = kMlpFeatures + 3 * kMlpHidden + 1;
+static __device__ __align__(256) float scratch[(size_t)kMlpNoAllocSamples * kInferFloats];
+
+float* mlp_scratch_address(int device) {
+  if (device < 0 || device >= 64) throw std::invalid_argument("device index out of range for the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != device) throw std::logic_error("scratch lookup with another device current");
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw std::runtime_error("hipGetSymbolAddress returned no address for the inference scratch");
+    g_scratch_ptr[device] = static_cast<float*>(p);
+  }
+  return g_scratch_ptr[device];
+}
 
 // ---------------------------------------------------------------- Mlp
 Mlp::~Mlp() {
@@ -336,6 +382,33 @@ void Mlp::train(hipStream_t st, const float* feat, const float* rank, int64_t n,
       for (int k = 0; k < steps_per_epoch; ++k) s += lh[(size_t)ep * steps_per_epoch + k];
       history[ep] = (float)(s / steps_per_epoch);
     }
+}
+
+// Queued on st only: nothing is allocated, copied to the host or waited for.
+// work: the device's inference scratch (mlp_scratch_address).  Features are
+// not checked (that would need a wait): a non-finite one gives a non-finite
+// rank.
+void Mlp::predict_device(hipStream_t st, const float* feat, int64_t n, float* rank_out, float* work) const {
+  if (!ready_) throw std::logic_error("predictor has no weights");
+  if (n < 0 || n > kMlpNoAllocSamples)
+    throw std::invalid_argument("sample count must be in 0.." + std::to_string(kMlpNoAllocSamples));
+  if (n == 0) return;
+  if (!feat || !rank_out || !work) throw std::invalid_argument("null device pointer");
+  const int B = (int)n;
+  float* x = work;
+  float* h1 = x + (size_t)B * kMlpFeatures;
+  float* h2 = h1 + (size_t)B * kMlpHidden;
+  float* h3 = h2 + (size_t)B * kMlpHidden;
+  float* y = h3 + (size_t)B * kMlpHidden;
+  FeatureNorm nm;
+  for (int f = 0; f < kMlpFeatures; ++f) {
+    nm.mu[f] = mu_[f];
+    nm.sd[f] = sd_[f];
+  }
+  hipLaunchKernelGGL(k_normalise, dim3(blocks((long)B * kMlpFeatures)), dim3(256), 0, st, feat, B, nm, x);
+  forward(st, x, B, h1, h2, h3, y);
+  hipLaunchKernelGGL(k_exp_rank, dim3(blocks(B)), dim3(256), 0, st, y, B, rank_out);
+  HIPCHK(hipGetLastError());
 }
 
 void Mlp::predict(hipStream_t st, const float* feat, int64_t n, float* rank_out) {

@@ -10,6 +10,8 @@
 namespace symhss {
 
 constexpr int kMlpFeatures = 6;
+// largest batch of the allocation-free inference (symhss_predictor_predict_noalloc)
+constexpr int kMlpNoAllocSamples = SYMHSS_PREDICT_NOALLOC_MAX;
 constexpr int kMlpHidden = 64;
 // 6*64+64 + 2*(64*64+64) + 64+1
 constexpr int kMlpParams = kMlpFeatures * kMlpHidden + kMlpHidden + 2 * (kMlpHidden * kMlpHidden + kMlpHidden) +
@@ -32,6 +34,8 @@ class Mlp {
                 float alpha, float* grad_host, float* loss_host);
   // rank_out[s] = exp(network output) for raw features feat[s * 6 ..]
   void predict(hipStream_t st, const float* feat, int64_t n, float* rank_out);
+  // the same with device pointers, activations in `work` (n <= kMlpNoAllocSamples)
+  void predict_device(hipStream_t st, const float* feat, int64_t n, float* rank_out, float* work) const;
 
  private:
   void alloc(int bmax);
@@ -43,5 +47,9 @@ class Mlp {
   double mu_[kMlpFeatures] = {0}, sd_[kMlpFeatures] = {1, 1, 1, 1, 1, 1};
   bool ready_ = false;
 };
+
+// Device address of the inference scratch on `device` (which must be
+// current), looked up once per device.
+float* mlp_scratch_address(int device);
 
 }  // namespace symhss

@@ -221,6 +221,7 @@ class Solver {
   void configure(int what, int64_t value);
   void hss_matvec(const symhss_z* x, symhss_z* y, int flags);
   Mlp& predictor() { return mlp_; }
+  float* infer_scratch() const { return infer_scratch_; }
   void box_table(int64_t* count, float* feat, int32_t* rank, int32_t* info) const;
   symhss_stats stats() const {
     symhss_stats s = stats_;
@@ -328,6 +329,7 @@ class Solver {
   std::vector<double> hx_, hy_;  // host copy of the nodes (planning)
   std::vector<double> hk_;       // curvature at the nodes (predictor features)
   Mlp mlp_;
+  float* infer_scratch_ = nullptr;  // this device's allocation-free inference scratch
   int use_predictor_ = 0, proxy_margin_ = 16;
   int rank_leaf_ = 0;        // fixed-rank schedule: k_L per half (0: tolerance mode)
   double rank_scale_ = 1.0;  // and the growth a per level
