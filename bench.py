@@ -378,9 +378,12 @@ def _run_mixed(args):
     print(f"mixed: FP64 {1e3 * t64:.1f} ms; mixed path", file=sys.stderr, flush=True)
     t32, st32, x32 = run(True)
     print(f"mixed: mixed {1e3 * t32:.1f} ms; residuals", file=sys.stderr, flush=True)
-    # FP32-only iterate
+    # FP32-only iterate (one refinement step: reported as not converged)
     s.configure(refine_maxit=1)
-    s.solve_device(b.data_ptr(), x.data_ptr())
+    st1 = s.lib.symhss_solve(s.h, binding.ctypes.c_void_p(b.data_ptr()), binding.ctypes.c_void_p(x.data_ptr()), 1,
+                             binding.DEVICE_PTRS)
+    if st1 not in (binding.OK, binding.ENOTCONV):
+        raise binding.SymhssError(st1, s.lib.symhss_last_error(s.h).decode())
     torch.cuda.synchronize()
     x1 = x.clone()
     s.configure(refine_maxit=10)

@@ -186,6 +186,42 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
   i = bi;
 }
 
+// Arg-max by 32-bit keys: a candidate's key is the upper word of its
+// non-negative FP64 magnitude (monotone in the magnitude, NaN above +inf)
+// with the low IDX_BITS + 1 bits replaced by a marker bit and
+// 2^IDX_BITS - 1 - i, so that the largest key names the largest magnitude
+// and, among magnitudes equal to about 2^-(19 - IDX_BITS) relative, the lowest
+// index i (0 <= i < 2^IDX_BITS).  Key 0 means "no candidate".  One 32-bit
+// maximum per exchange instead of a value and an index.
+template <int IDX_BITS>
+__device__ __forceinline__ unsigned argmax_key(double v, int i) {
+  if (!(v >= 0.0) && v == v) return 0u;  // negative: no candidate (NaN is a candidate)
+  constexpr unsigned low = (2u << IDX_BITS) - 1u;
+  const unsigned hi = (unsigned)(__double_as_longlong(v) >> 32);
+  return (hi & ~low) | (1u << IDX_BITS) | ((1u << IDX_BITS) - 1u - (unsigned)i);
+}
+template <int IDX_BITS>
+__device__ __forceinline__ int argmax_key_index(unsigned k) {
+  return (int)((1u << IDX_BITS) - 1u - (k & ((1u << IDX_BITS) - 1u)));
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_max_u32(unsigned k) {
+  const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, CTRL, 0xF, 0xF, false);
+  return o > k ? o : k;
+}
+// Largest key over the 64 lanes (every lane receives it): DPP exchanges
+// within rows of 16, then the four rows by readlane.
+__device__ __forceinline__ unsigned wave_max_key(unsigned k) {
+  k = dpp_max_u32<0xB1>(k);   // quad_perm [1, 0, 3, 2]
+  k = dpp_max_u32<0x4E>(k);   // quad_perm [2, 3, 0, 1]
+  k = dpp_max_u32<0x141>(k);  // row_half_mirror
+  k = dpp_max_u32<0x140>(k);  // row_mirror
+  const unsigned a = __builtin_amdgcn_readlane(k, 0), b = __builtin_amdgcn_readlane(k, 16);
+  const unsigned c = __builtin_amdgcn_readlane(k, 32), d = __builtin_amdgcn_readlane(k, 48);
+  const unsigned ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
 // Sum over the 64 lanes of a wavefront; every lane receives the same value.
 // Row sums by the DPP exchanges of wave_argmax, then the four row sums in
 // lane order.

@@ -157,21 +157,37 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
   double r00 = (j0 > 0) ? *D.r00 : 0.0;
   int j = j0;
   for (; j < kmax; ++j) {
-    // pivot: the position t >= j of largest trailing norm, lowest t on ties
+    // pivot: the position t >= j of largest trailing norm.  Each thread's
+    // best position exactly (lowest t on ties), then 32-bit arg-max keys over
+    // the wavefront (the lane in the key: norms equal to about 2^-13 relative
+    // go to the lowest lane) and over the wavefronts (lowest wavefront)
     double best = -1.0;
-    int bi = n;
+    int bt = n;
     for (int t = j + tid; t < n; t += NT) {
       const double x = vn[pos[t]];
-      if (x > best) { best = x; bi = t; }
+      if (x > best || (x != x && best == best)) {
+        best = x;
+        bt = t;
+      }
     }
-    wave_argmax(best, bi);
-    if (lane == 0) { red[wave] = best; redi[wave] = bi; }
+    const unsigned key = wave_max_key(argmax_key<6>(best, lane));
+    unsigned* redk = reinterpret_cast<unsigned*>(red);
+    if (key != 0u && lane == argmax_key_index<6>(key)) {
+      redk[wave] = key;
+      redi[wave] = bt;
+    } else if (key == 0u && lane == 0) {
+      redk[wave] = 0u;
+    }
     __syncthreads();
-    double b = red[0];
-    int p = redi[0];
+    unsigned kb = redk[0];
+    int p = kb ? redi[0] : n;
 #pragma unroll
     for (int w = 1; w < nwaves; ++w)
-      if (red[w] > b || (red[w] == b && redi[w] < p)) { b = red[w]; p = redi[w]; }
+      if (redk[w] > kb) {
+        kb = redk[w];
+        p = redi[w];
+      }
+    const double b = kb ? vn[pos[p]] : -1.0;
     const double nrm = sqrt(b > 0.0 ? b : 0.0);
     if (j == 0) r00 = nrm;
     int stop;
@@ -348,6 +364,7 @@ void launch_cpqr(hipStream_t st, const IdDesc* descs, int count, int mmax, int n
   if (count <= 0) return;
   const size_t lds = cpqr_lds_bytes(mmax, nmax);
   if (lds > 160 * 1024) throw std::runtime_error("proxy matrix too large for the ID kernel's LDS staging");
+
   int* q = var.persistent ? queue : nullptr;
   if (var.persistent) {
     if (!queue) throw std::invalid_argument("persistent ID launch without a queue counter");

@@ -119,6 +119,36 @@ class Uploader {
   Chunk& new_chunk(size_t cap);
 };
 
+// Workspace of the multi-workgroup LU for one batched launch: F, the row
+// positions and counters, the panel's triangular inverses.
+template <class C>
+struct CaluWs {
+  DBuf<C> F, tw;
+  DBuf<int> iw;
+  // size the buffers for the descriptors and point each descriptor at its part
+  template <class D>
+  void attach(std::vector<D>& v) {
+    size_t fe = 0, ie = 0, te = 0;
+    for (const D& d : v) {
+      fe += (size_t)d.n * d.ncol;
+      ie += (size_t)calu_iw_ints(d.n);
+      te += (size_t)calu_tw_elems(d.ncol);
+    }
+    F.ensure(std::max<size_t>(fe, 1));
+    iw.ensure(std::max<size_t>(ie, 1));
+    tw.ensure(std::max<size_t>(te, 1));
+    fe = ie = te = 0;
+    for (D& d : v) {
+      d.F = F.p + fe;
+      d.iw = iw.p + ie;
+      d.tw = tw.p + te;
+      fe += (size_t)d.n * d.ncol;
+      ie += (size_t)calu_iw_ints(d.n);
+      te += (size_t)calu_tw_elems(d.ncol);
+    }
+  }
+};
+
 // Geometry of one box of a boundary's full binary tree.
 struct BoxGeom {
   int lo = 0, hi = 0;  // node range (global node ids)
@@ -175,6 +205,10 @@ struct Level {
   DBuf<cplx> gen;
   DBuf<f32::cplx> aug1f, aug2f, interpf;
   DBuf<f32::cplx> Ff, Gf, Ftf, Zf;
+  // multi-workgroup LU workspaces of the two factorisations (FP64, FP32)
+  CaluWs<cplx> cw1, cw2;
+  CaluWs<f32::cplx> cw1f, cw2f;
+  int netperm1 = 0;  // the LU of [D | L] left a net permutation (multi-workgroup LU)
   size_t s_total = 0, k_total = 0;
 };
 
@@ -277,8 +311,11 @@ class Solver {
   // launches with a choice of variant (autotuned per size bucket when enabled)
   void run_cpqr(const IdDesc* d, int count, int mmax, int nmax, int want_T, cplx* data, size_t data_elems, int* ints,
                 size_t nints, double* dbl, size_t ndbl);
-  void run_lu(const LuDesc* d, int count, int nmax, int ncolmax, int nrhsmax, cplx* data, size_t data_elems,
-              int* info, int ninfo, double flops);
+  // returns 1 if the multi-workgroup LU ran (net permutation in the pivots),
+  // 0 for k_lu_fused (row interchanges); multi_ok: the descriptors carry the
+  // multi-workgroup LU's workspace
+  int run_lu(const LuDesc* d, int count, int nmax, int ncolmax, int nrhsmax, cplx* data, size_t data_elems,
+             double flops, bool multi_ok);
   void solve_enqueue(const cplx* db, cplx* dx, int nrhs);
   // the solve of device vectors (graph replay, mixed-precision refinement);
   // false if a refinement stopped at its iteration limit above its target
@@ -340,6 +377,9 @@ class Solver {
   int Htop_ = 0;            // highest height holding boxes (max over trees of root_h)
   std::vector<Level> hev_;  // index = height (0 = leaves)
   DBuf<cplx> root_;         // dense top-level systems of all trees
+  CaluWs<cplx> rootcw_;
+  CaluWs<f32::cplx> rootcwf_;
+  int root_netperm_ = 0;    // their LU left a net permutation (multi-workgroup LU)
   DBuf<int> rootpiv_, rootinfo_;
   size_t rootvec_total_ = 0;  // sum of the trees' root orders
   DBuf<cplx> rootF_, rootG_;

@@ -75,8 +75,14 @@ def test_refined_multiple_rhs_and_single_iteration():
     s.factor()
     X = s.solve(B)
     assert rel(X, dense.solve_dense(A, B)) < 1e-8
+    # one FP32 solve: above the 1e-10 target, so the call reports ENOTCONV and
+    # hands back that iterate
+    from paper_2609_33216_amd import binding
     s.configure(refine_maxit=1)
-    x1 = s.solve(b)
+    bb = np.asfortranarray(b.reshape(-1, 1))
+    xx = np.zeros_like(bb, order="F")
+    assert s.lib.symhss_solve(s.h, binding._ptr(bb), binding._ptr(xx), 1, 0) == binding.ENOTCONV
+    x1 = xx[:, 0]
     st = s.stats()
     e1 = rel(x1, dense.solve_dense(A, b))
     print("FP32-only iterate: residual", st["fp32_residual"], "error", e1)
