@@ -96,6 +96,7 @@ def _run_form(s, wl, form, steps, warmup, b, x, torch, root_max=0):
         s.solve_device(b.data_ptr(), x.data_ptr())
     torch.cuda.synchronize()
     per = []
+    phases = {"t_compress": [], "t_factor": [], "t_solve": []}
     t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
@@ -104,8 +105,15 @@ def _run_form(s, wl, form, steps, warmup, b, x, torch, root_max=0):
         s.solve_device(b.data_ptr(), x.data_ptr())
         torch.cuda.synchronize()
         per.append(time.perf_counter() - ts)
+        st = s.stats()
+        for k in phases:
+            phases[k].append(st[k])
     t1 = time.perf_counter()
-    return (t1 - t0) / max(steps, 1), s.stats(), per
+    st = s.stats()
+    # phase times: the mean over the timed steps (the last step's kernel timings stay in st)
+    for k, v in phases.items():
+        st[k] = sum(v) / max(len(v), 1)
+    return (t1 - t0) / max(steps, 1), st, per
 
 
 def _cpu_baseline(wl):
@@ -138,11 +146,20 @@ def _cpu_baseline(wl):
     t_lu = time.perf_counter() - t0
     t_lu_full = t_lu * (2 * n / m) ** 3
     total = t_assembly + t_lu_full
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": round(total, 3), "unit": "s/solve", "cores": int(cores), "kind": "oracle",
-        "sample": (f"oracle dense assembly of {rows} of {n} node rows (x{n / rows:.0f}) plus "
-                   f"scipy LU of a {m}x{m} complex system (x{(2 * n / m) ** 3:.0f} by n^3), "
-                   f"extrapolated to the dense {2 * n}-unknown solve; assembly {t_assembly:.1f} s, "
+        "extrapolated": True, "cpu_model": model,
+        "sample": (f"extrapolated from samples: oracle dense assembly of {rows} of {n} node rows "
+                   f"(x{n / rows:.0f}) plus scipy LU of a {m}x{m} complex system (x{(2 * n / m) ** 3:.0f} "
+                   f"by n^3) to the dense {2 * n}-unknown solve; assembly {t_assembly:.1f} s, "
                    f"LU {t_lu_full:.1f} s"),
         "gentries_per_s": round(4.0 * rows * n / t_rows / 1e9, 5),
     }
@@ -570,6 +587,8 @@ def main():
     ap.add_argument("--no-base", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-residual", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="skip the untimed relative-error check against the stored dense-LU solution")
     ap.add_argument("--no-graphs", action="store_true", help="batch mode: no HIP-graph replay")
     ap.add_argument("--no-single", action="store_true", help="batch mode: skip the one-at-a-time sum")
     ap.add_argument("--no-pipeline", action="store_true",
@@ -695,17 +714,58 @@ def main():
                            "unit": d["unit"], "frac": d["frac"], "traffic": _traffic(dom, wl.name),
                            "avg_launch_us": round(1e6 * d["seconds"] / max(d["launches"], 1), 1)}
         out["kernel_rooflines"] = rl
+    lm = rl.get("lu_multi (several kernels)")
+    if lm:
+        # beside the single-kernel roofline: the multi-workgroup LU sequences
+        # (dense top-level system and the top levels' blocks), whose time per
+        # step exceeds any single kernel's
+        out["roofline_lu_multi"] = {"kernels": "k_calu_* sequence per call", "bound": "alu",
+                                    "achieved": lm["achieved"], "peak": lm["peak"], "unit": lm["unit"],
+                                    "frac": lm["frac"], "calls": lm["launches"],
+                                    "avg_call_us": round(1e6 * lm["seconds"] / max(lm["launches"], 1), 1)}
 
     if not args.no_base:
-        t_base, stb, _ = _run_form(s, wl, binding.MULLER_BASE, 1, 1, b, x, torch, rm)
+        # the unscaled two-sided baseline over the same steps and warm-up
+        t_base, stb, _ = _run_form(s, wl, binding.MULLER_BASE, args.steps, args.warmup, b, x, torch, rm)
         out["nonsym"] = {"s_per_solve": round(t_base, 6), "t_compress": round(stb["t_compress"], 6),
-                         "t_factor": round(stb["t_factor"], 6),
-                         "entries": int(stb["entries_compress"] + stb["entries_factor"])}
+                         "t_factor": round(stb["t_factor"], 6), "t_solve": round(stb["t_solve"], 6),
+                         "t_compress_host": round(stb["t_compress"] - stb["t_compress_wait"], 6),
+                         "kernel_seconds": {"kblock": round(stb["t_kblock_compress"] + stb["t_kblock_factor"], 6),
+                                            "id": round(stb["t_id"], 6), "lu": round(stb["t_lu"], 6)},
+                         "entries": int(stb["entries_compress"] + stb["entries_factor"]),
+                         "steps": args.steps}
         out["speedup_sym_vs_nonsym"] = {"compress": round(stb["t_compress"] / st["t_compress"], 3),
-                                        "total": round(t_base / t_sym, 3)}
+                                        "total": round(t_base / t_sym, 3),
+                                        "id_kernels": round(stb["t_id"] / st["t_id"], 3) if st["t_id"] > 0 else None,
+                                        "entries": round(out["nonsym"]["entries"] / max(out["entries"], 1), 3)}
+    if not args.no_parity:
+        out["rel_err_vs_dense_oracle"] = _parity_vs_golden(s, wl, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = _cpu_baseline(wl)
     print(json.dumps(out))
+
+
+def _parity_vs_golden(s, wl, torch):
+    """Untimed: the same path on the same curve and wavenumbers at a size whose
+    dense-LU solution the oracle stored (tests/golden), relative 2-norm error."""
+    import numpy as np
+    import workloads
+    from paper_2609_33216_amd import binding
+    out = {}
+    for n in (16384,):
+        path = os.path.join(ROOT, "tests", "golden", f"star5_k50-75_n{n}_dense_x.npy")
+        if wl.name != "star5-n32768-k50-75" or not os.path.exists(path):
+            return None
+        xd = np.load(path, allow_pickle=False)
+        w = workloads.config2_reduced(n)
+        x_, dx_, ddx_ = w.boundary()
+        s.assemble(x_, dx_, ddx_, w.k0, w.k1, w.eps0, w.eps1, leaf=w.leaf, tol=w.tol, form=binding.MULLER_SYM)
+        b = s.rhs_plane_wave(w.angle)
+        s.compress()
+        s.factor()
+        xg = s.solve(b)
+        out[f"n{n}"] = float(np.linalg.norm(xg - xd) / np.linalg.norm(xd))
+    return out
 
 
 if __name__ == "__main__":

@@ -303,7 +303,10 @@ class Solver {
   void factor_layout();
   void factor_layout_level(int h);
   void factor_layout_root();
-  void enqueue_on_factor_stream(const std::function<void()>& f);
+  // f's launches go to the factor stream, after `after` (null: after
+  // everything queued on the compress stream so far)
+  void enqueue_on_factor_stream(const std::function<void()>& f, hipEvent_t after = nullptr);
+  void queue_pending_factor();
   void factor_level(int h);
   void factor_root();
   void factor_enqueue();
@@ -427,6 +430,8 @@ class Solver {
   // pipelining: per-level factor work on a second stream during compress
   hipStream_t fst_ = nullptr;
   hipEvent_t cev_ = nullptr;
+  hipEvent_t fev_ = nullptr;   // end of the compression of height pending_factor_
+  int pending_factor_ = -1;    // compressed height whose pipelined factorisation is not queued yet
   Uploader fup2_;
   int pipeline_opt_ = 1;
   bool pipelined_ = false;
