@@ -226,7 +226,7 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
  *       of the tolerance rule; 0: tolerance mode.
  *  SYMHSS_OPT_RANK_SCALE [1000] the growth a per level, times 1000 (1000..4000).
  *       Both require a new symhss_compress.
- *  SYMHSS_OPT_PIPELINE    [1] 1: in FP64, symhss_compress already queues
+ *  SYMHSS_OPT_PIPELINE    [1] 1: (either precision) symhss_compress already queues
  *       each level's factorisation on a second stream as soon as the level's
  *       IDs are known (it overlaps the planning of the next level);
  *       symhss_factor then adds the top-level systems and waits.  Such a

@@ -435,6 +435,7 @@ class Solver {
   Uploader fup2_;
   int pipeline_opt_ = 1;
   bool pipelined_ = false;
+  int pipelined_precision_ = 0;  // precision the pipelined factorisation was queued in
   std::vector<hipEvent_t> event_pool_;
   symhss_stats stats_{};
 };
