@@ -201,10 +201,15 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
  *       timings in the statistics are not collected for replays.
  *  SYMHSS_OPT_AUTOTUNE    [0] 1: the first ID and LU launch of each size bucket
  *       (count, rows, columns) times every launch variant on the real data
- *       (restored between trials) and keeps the fastest; all variants give
- *       the same result.
- *  SYMHSS_OPT_PERSISTENT [-1] ID grid: 0 one workgroup per matrix, 1 a
- *       persistent grid taking matrices from a work queue, -1 automatic.
+ *       (restored between trials) and keeps the fastest.  The variants
+ *       compute the same pivoted QR with different summation orders (the
+ *       ID also as a blocked QR followed by the pivoted QR of its triangle),
+ *       so ranks and skeletons agree up to rounding.
+ *  SYMHSS_OPT_PERSISTENT [-1] ID kernel: -1 automatic (the blocked QR and
+ *       the pivoted QR of its triangle in registers for proxy matrices of at
+ *       most 512 rows and 128 columns, else the one-stage kernel); 0 the
+ *       one-stage kernel with one workgroup per matrix, 1 the one-stage
+ *       kernel as a persistent grid taking matrices from a work queue.
  *  SYMHSS_OPT_PREDICTOR   [0] 1: proxy counts from the rank predictor (below).
  *  SYMHSS_OPT_PROXY_MARGIN [16] proxy points added to the predicted rank.
  *  SYMHSS_OPT_PRECISION   [0] 1: mixed precision.  The IDs and every kernel

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libsymhss.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["kblock.hip", "cpqr.hip", "dense.hip", "dense32.hip", "mixed.hip", "mlp.hip", "upload.hip", "solver.cpp",
+SOURCES = ["kblock.hip", "cpqr.hip", "idqr.hip", "dense.hip", "dense32.hip", "mixed.hip", "mlp.hip", "upload.hip", "solver.cpp",
            "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

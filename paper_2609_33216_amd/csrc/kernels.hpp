@@ -55,11 +55,18 @@ size_t cpqr_lds_bytes(int mmax, int nmax);
 struct CpqrVariant {
   int threads = 256;   // 256 or 1024 per workgroup
   int persistent = 0;  // 1: work-queue grid (needs a device counter)
+  int qr = 0;          // 1: blocked QR, then pivoted QR of the triangle in registers (idqr.hip)
 };
-CpqrVariant cpqr_default_variant(int count);
-// queue: one device int, used (and zeroed first) by persistent variants
+CpqrVariant cpqr_default_variant(int count, int mmax, int nmax);
+// queue: one device int, used (and zeroed first) by persistent variants;
+// resume: a pass that continues the IDs a previous launch of the same
+// variant stopped (targets set, rank = steps done)
 void launch_cpqr(hipStream_t st, const IdDesc* descs, int count, int mmax, int nmax, double tol, int want_T,
-                 const CpqrVariant& var, int* queue);
+                 const CpqrVariant& var, int* queue, bool resume);
+// the two-stage ID of idqr.hip: matrices of at most 128 columns and 512 rows
+bool id_qr_eligible(int mmax, int nmax);
+void launch_id_qr(hipStream_t st, const IdDesc* descs, int count, int mmax, int nmax, double tol, int want_T,
+                  bool resume);
 void launch_build_interp(hipStream_t st, const InterpDesc* descs, int count, int nmax);
 void launch_equalise_ranks(hipStream_t st, int npairs, const int* ia, const int* ib, IdDesc* descs);
 

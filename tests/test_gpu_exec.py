@@ -3,8 +3,10 @@ autotuner and HIP-graph replay of factorisations and solves.
 
 * The work-queue grid runs the same per-matrix arithmetic as one workgroup
   per matrix: solutions are bit-identical.
-* The autotuner may pick another LU schedule (different summation order):
-  solutions agree to 1e-12 and stay within 1e-8 of the dense oracle.
+* The autotuner may pick another LU schedule or ID kernel (different
+  summation orders; an ID may then settle a near-tie of column norms the
+  other way and keep another, equally valid skeleton): solutions agree to
+  1e-9, about the ID tolerance, and stay within 1e-8 of the dense oracle.
 * Graph replays are checked on every replay against the eager result of the
   same structure (bit-identical: same kernels, same data), with eager work
   and synchronisation between replays, and a changed structure is not
@@ -57,7 +59,7 @@ def test_autotuned_matches():
     x1 = _solve(s1, b)
     assert s1.stats()["tuned_buckets"] > 0
     x2 = _solve(s1, b)  # tuned choices reused
-    assert rel(x1, x0) < 1e-12
+    assert rel(x1, x0) < 1e-9
     assert np.array_equal(x1, x2)
     assert rel(x1, dense.solve_dense(A, b)) < 1e-8
 
@@ -157,12 +159,13 @@ def test_pipelined_factor_bit_identical():
     assert np.array_equal(s1.solve(b), x0)
     s1.factor()
     assert np.array_equal(s1.solve(b), x0)
-    # autotuned LU trials run on the factor stream
+    # autotuned LU trials run on the factor stream (the tuned ID kernel may
+    # keep other, equally valid skeletons: agreement to about the ID tolerance)
     s2 = make_solver(wl)
     s2.configure(pipeline=True, autotune=True)
     for _ in range(2):
         x2 = _solve(s2, b)
-        assert rel(x2, x0) < 1e-12
+        assert rel(x2, x0) < 1e-9
     # precision switched after a pipelined compress: factor redoes the levels
     s1.compress()
     s1.configure(mixed=True)
