@@ -50,13 +50,16 @@ MI355X_HBM_TBS = 8.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs of
 # this script (star5-n32768-k50-75, one step), scaled by the same counters read
 # on a plain 512 MiB copy (fetch x2.0, write x1.0).  Valid only while the
-# kernel's source is the one profiled: keyed by the SHA-256 prefix of its file.
+# kernels' sources are the ones profiled: keyed by the SHA-256 prefixes of
+# their files.  An ID launch is the blocked QR and the pivoted QR of its
+# triangle (k_id_qr + k_id_sq) for many matrices, or k_cpqr for few; its
+# figure is the mean over the five ID launches of a step.
 MEASURED_TRAFFIC = {
-    "k_cpqr": {"source": "cpqr.hip", "sha": "7e2412fc039566bb", "bytes": 3.002e+09,
-               "profile": "profiles/k_cpqr_star5-n32768.md"},
-    "k_lu_fused": {"source": "dense_body.inc", "sha": "987bfe5305885f7a", "bytes": 7.706e+08,
+    "id": {"sources": {"idqr.hip": "d897b70432302afa", "cpqr.hip": "f51c6ca6f3a5b966"}, "bytes": 7.69e+08,
+           "profile": "profiles/id_star5-n32768.md"},
+    "k_lu_fused": {"sources": {"dense_body.inc": "545400a3d12683a1"}, "bytes": 7.464e+08,
                    "profile": "profiles/k_lu_fused_star5-n32768.md"},
-    "k_kblock": {"source": "kblock.hip", "sha": "840bcffe0b166028", "bytes": 7.431e+07,
+    "k_kblock": {"sources": {"kblock.hip": "b8965c325ada25df"}, "bytes": 7.425e+07,
                  "profile": "profiles/k_kblock_star5-n32768.md"},
 }
 
@@ -66,12 +69,14 @@ def _traffic(kernel: str, workload: str):
     t = MEASURED_TRAFFIC.get(kernel)
     if t is None or workload != "star5-n32768-k50-75":
         return None
-    src = os.path.join(ROOT, "paper_2609_33216_amd", "csrc", t["source"])
-    try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    except OSError:
-        return None
-    return t["bytes"] if sha == t["sha"] else None
+    for name, sha in t["sources"].items():
+        src = os.path.join(ROOT, "paper_2609_33216_amd", "csrc", name)
+        try:
+            if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != sha:
+                return None
+        except OSError:
+            return None
+    return t["bytes"]
 
 
 def _workload(cfg: int):
@@ -695,7 +700,7 @@ def main():
         a = st["bytes_kblock"] / t_kb / 1e9
         rl["k_kblock"] = {"bound": "hbm", "achieved": a, "peak": MI355X_HBM_TBS * 1e3, "unit": "GB/s",
                           "seconds": t_kb, "launches": st["n_kblock"]}
-    for name, t, f, nl in (("k_cpqr", st["t_id"], st["flops_id"], st["n_id"]),
+    for name, t, f, nl in (("id", st["t_id"], st["flops_id"], st["n_id"]),
                            ("k_lu_fused", st["t_lu_batched"], st["flops_lu_batched"], st["n_lu_batched"]),
                            ("lu_multi (several kernels)", st["t_lu_multi"], st["flops_lu_multi"], st["n_lu_multi"])):
         if t > 0:
@@ -705,7 +710,7 @@ def main():
         v["frac"] = round(v["achieved"] / v["peak"], 4)
         v["achieved"] = round(v["achieved"], 3)
         v["seconds"] = round(v["seconds"], 6)
-    single = [k for k in ("k_kblock", "k_cpqr", "k_lu_fused") if k in rl]
+    single = [k for k in ("k_kblock", "id", "k_lu_fused") if k in rl]
     if single:
         # the single kernel with the most event time per step
         dom = max(single, key=lambda k: rl[k]["seconds"])
