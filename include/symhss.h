@@ -200,8 +200,10 @@ symhss_status symhss_matvec_direct(symhss_ctx *ctx, const symhss_z *x, symhss_z 
  *       device-pointer solve repeated with the same vectors and nrhs.  Kernel
  *       timings in the statistics are not collected for replays.
  *  SYMHSS_OPT_AUTOTUNE    [0] 1: the first ID and LU launch of each size bucket
- *       (count, rows, columns) times every launch variant on the real data
- *       (restored between trials) and keeps the fastest.  The variants
+ *       (count, rows, columns), and the first product of the solve sweeps with
+ *       at most four right-hand sides in each bucket (64 x 64 matrix-core tile
+ *       or the skinny 64-row kernel), times every launch variant on the real
+ *       data (restored between trials) and keeps the fastest.  The variants
  *       compute the same pivoted QR with different summation orders (the
  *       ID also as a blocked QR followed by the pivoted QR of its triangle),
  *       so ranks and skeletons agree up to rounding.

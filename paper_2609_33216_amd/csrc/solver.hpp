@@ -312,6 +312,8 @@ class Solver {
   void factor_enqueue();
   uint64_t plan_signature() const;
   // launches with a choice of variant (autotuned per size bucket when enabled)
+  template <class S>
+  void run_gemm(const std::vector<typename S::GemmDesc>& g, int count, int mmax, int nmax);
   void run_cpqr(const IdDesc* d, int count, int mmax, int nmax, int want_T, cplx* data, size_t data_elems, int* ints,
                 size_t nints, double* dbl, size_t ndbl);
   // returns 1 if the multi-workgroup LU ran (net permutation in the pivots),
