@@ -275,6 +275,17 @@ class Solver {
   void build_tree();
   void set_active(int h);
   void plan_proxy_near(int h);
+  void plan_proxy(int h);  // proxy circles (geometry and the predictor)
+  void plan_near(int h);   // near fields (active sets of the neighbours)
+  // Height h built ahead, while height h - 1's IDs run: boxes, proxy circles
+  // and proxy points of the trees that may continue (those below their last
+  // height).  Kept when exactly those trees continue, else rebuilt.
+  void preplan(int h);
+  int preplanned_h_ = -1;
+  std::vector<int> preplanned_trees_;
+  // proxy points of the current pass: offsets of each box's points
+  void proxy_points(int h, const std::vector<int>& which);
+  std::vector<int> prox_off_;
   void add_height(int h, const std::vector<int>& trees);
   int level_of(int h) const { return Lmax_ - h; }
   const Box& child(int h, const Box& B, int w) const {
@@ -296,7 +307,8 @@ class Solver {
     int per = 2;
   };
   IdPass pass_[2];  // [0] all boxes, [1] predictor fallbacks
-  void proxy_ids(int h, const std::vector<int>& which, IdPass& P);
+  // points_ready: proxy_points already ran for these boxes
+  void proxy_ids(int h, const std::vector<int>& which, IdPass& P, bool points_ready = false);
   void box_features_of(int h, const Box& B, float* f) const;
   // factor pieces
   void factor_impl();
