@@ -102,6 +102,18 @@ class Uploader {
     return static_cast<T*>(put_bytes(v.data(), v.size() * sizeof(T)));
   }
   void* put_bytes(const void* src, size_t bytes);
+  // Several arrays in one copy: stage() reserves staging space (h: host
+  // address, hd: the same bytes as the device reads them, d: the device
+  // copy), the caller fills h, and commit() queues the copy from h to d.  A
+  // kernel of the caller's may instead read hd directly, without commit().
+  struct Span {
+    char* h;
+    char* hd;
+    char* d;
+    size_t bytes;
+  };
+  Span stage(size_t bytes);
+  void commit(const Span& s);
   void reset();
   size_t used() const;
   // one chunk with at least `bytes` free, so that later puts allocate nothing
