@@ -234,6 +234,7 @@ struct Tree {
   int root_h = -1;          // height of the dense top-level system
   int root_n = 0;           // its order
   size_t root_off = 0;      // offset of its matrix in the root buffer
+  size_t root_inv_off = 0;  // offset of its diagonal-block inverses (blocked substitution)
   size_t rootvec_off = 0;   // offset of its unknowns in the root vectors
 };
 
@@ -410,6 +411,12 @@ class Solver {
   CaluWs<f32::cplx> rootcwf_;
   int root_netperm_ = 0;    // their LU left a net permutation (multi-workgroup LU)
   DBuf<int> rootpiv_, rootinfo_;
+  // inverses of the 64 x 64 diagonal blocks of the top-level LU factors, for
+  // the blocked substitution of systems of order kTrsvMinOrder and more
+  DBuf<cplx> root_inv_;
+  DBuf<f32::cplx> root_invf_;
+  static constexpr int kTrsvMinOrder = 512;
+  void root_invert();
   size_t rootvec_total_ = 0;  // sum of the trees' root orders
   DBuf<cplx> rootF_, rootG_;
   // mixed precision
