@@ -74,6 +74,37 @@ __host__ __device__ inline void fma_conj_acc(cplxf& a, cplxf b, cplxf c) {
   a.re = fmaf(b.re, c.re, fmaf(b.im, c.im, a.re));
   a.im = fmaf(b.re, c.im, fmaf(-b.im, c.re, a.im));
 }
+// Accesses through pointers known to address global memory.  A pointer read
+// from a descriptor in memory is generic, so the compiler emits flat
+// instructions for it; a flat access counts against the LDS counter too, and
+// the compiler then waits for every flat access in flight before it uses an
+// LDS result (and the reverse), so that global loads cannot overlap LDS work
+// or each other.  These helpers load and store through the global address
+// space instead.  Only for pointers into device memory (never LDS or stack).
+#define SYMHSS_GLOBAL_AS __attribute__((address_space(1)))
+typedef double symhss_v2d __attribute__((ext_vector_type(2)));
+typedef float symhss_v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cplx ldg(const cplx* p) {
+  const symhss_v2d v = *(const SYMHSS_GLOBAL_AS symhss_v2d*)p;
+  return cplx{v.x, v.y};
+}
+__device__ __forceinline__ void stg(cplx* p, cplx c) {
+  const symhss_v2d v = {c.re, c.im};
+  *(SYMHSS_GLOBAL_AS symhss_v2d*)p = v;
+}
+__device__ __forceinline__ cplxf ldg(const cplxf* p) {
+  const symhss_v2f v = *(const SYMHSS_GLOBAL_AS symhss_v2f*)p;
+  return cplxf{v.x, v.y};
+}
+__device__ __forceinline__ void stg(cplxf* p, cplxf c) {
+  const symhss_v2f v = {c.re, c.im};
+  *(SYMHSS_GLOBAL_AS symhss_v2f*)p = v;
+}
+__device__ __forceinline__ int ldg(const int* p) { return *(const SYMHSS_GLOBAL_AS int*)p; }
+__device__ __forceinline__ void stg(int* p, int v) { *(SYMHSS_GLOBAL_AS int*)p = v; }
+__device__ __forceinline__ double ldg(const double* p) { return *(const SYMHSS_GLOBAL_AS double*)p; }
+__device__ __forceinline__ void stg(double* p, double v) { *(SYMHSS_GLOBAL_AS double*)p = v; }
+
 __host__ __device__ inline cplxf cdiv(cplxf a, cplxf b) {
   if (fabsf(b.re) >= fabsf(b.im)) {
     const float r = b.im / b.re, d = b.re + b.im * r;
