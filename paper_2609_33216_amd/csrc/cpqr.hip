@@ -49,7 +49,7 @@ __device__ inline void reflect_columns(const IdDesc& D, int j, const int* pc, in
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int i = lane + 64 * q;
-      a[b][q] = (c[b] >= 0 && i < rows) ? col[i] : mk(0, 0);
+      a[b][q] = (c[b] >= 0 && i < rows) ? ldg(col + i) : mk(0, 0);
     }
   }
 #pragma unroll
@@ -79,7 +79,7 @@ __device__ inline void reflect_columns(const IdDesc& D, int j, const int* pc, in
         const cplx vi = vj[i];
         a[b][q].re -= vi.re * tw.re - vi.im * tw.im;
         a[b][q].im -= vi.re * tw.im + vi.im * tw.re;
-        col[i] = a[b][q];
+        stg(col + i, a[b][q]);
         if (i > 0) s[b] += abs2(a[b][q]);
       }
     }
@@ -100,17 +100,17 @@ __device__ inline void reflect_column_long(const IdDesc& D, int j, int c, const 
   const int rows = D.m - j;
   cplx* col = D.A + (long)D.ld * c + j;
   cplx w = mk(0, 0);
-  for (int i = lane; i < rows; i += 64) fma_conj_acc(w, vj[i], col[i]);
+  for (int i = lane; i < rows; i += 64) fma_conj_acc(w, vj[i], ldg(col + i));
   w.re = wave_sum(w.re);
   w.im = wave_sum(w.im);
   const cplx tw = tau * w;
   double s = 0.0;
   for (int i = lane; i < rows; i += 64) {
-    cplx a = col[i];
+    cplx a = ldg(col + i);
     const cplx vi = vj[i];
     a.re -= vi.re * tw.re - vi.im * tw.im;
     a.im -= vi.re * tw.im + vi.im * tw.re;
-    col[i] = a;
+    stg(col + i, a);
     if (i > 0) s += abs2(a);
   }
   s = wave_sum(s);
@@ -141,20 +141,20 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
   __shared__ double s_tau;
 
   const int kmax = m < n ? m : n;
-  const int j0 = (D.target >= 0) ? *D.rank : 0;
-  for (int c = tid; c < n; c += NT) pos[c] = (j0 == 0) ? c : D.perm[c];
+  const int j0 = (D.target >= 0) ? ldg(D.rank) : 0;
+  for (int c = tid; c < n; c += NT) pos[c] = (j0 == 0) ? c : ldg(D.perm + c);
   __syncthreads();
   // trailing norms over rows j0..m-1 of the columns not yet pivoted
   for (int t = j0 + wave; t < n; t += nwaves) {
     const int c = pos[t];
     const cplx* col = D.A + ld * c;
     double s = 0.0;
-    for (int i = j0 + lane; i < m; i += 64) s += abs2(col[i]);
+    for (int i = j0 + lane; i < m; i += 64) s += abs2(ldg(col + i));
     s = wave_sum(s);
     if (lane == 0) vn[c] = s;
   }
   __syncthreads();
-  double r00 = (j0 > 0) ? *D.r00 : 0.0;
+  double r00 = (j0 > 0) ? ldg(D.r00) : 0.0;
   int j = j0;
   for (; j < kmax; ++j) {
     // pivot: the position t >= j of largest trailing norm.  Each thread's
@@ -194,7 +194,7 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
     if (D.target >= 0) stop = (j >= D.target);
     else stop = !(r00 > 0.0) || !(nrm > tol * r00);  // NaN-safe
     if (p >= n) stop = 1;  // no admissible pivot (non-finite norms)
-    if (j == 0 && tid == 0) *D.r00 = r00;
+    if (j == 0 && tid == 0) stg(D.r00, r00);
     if (stop) break;  // uniform: every thread decided from the same slots
     // Householder reflector H = I - tau v v^H with v_0 = 1 mapping the pivot
     // column's trailing part y = [alpha; x] to beta e_1, beta = -e^{i arg alpha} |y|.
@@ -202,9 +202,9 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
       const int cp = pos[p];
       cplx* cj = D.A + ld * cp;
       double s = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) s += abs2(cj[i]);
+      for (int i = j + 1 + lane; i < m; i += 64) s += abs2(ldg(cj + i));
       s = wave_sum(s);
-      const cplx alpha = cj[j];
+      const cplx alpha = ldg(cj + j);
       const double aa = sqrt(abs2(alpha));
       const double nr = sqrt(aa * aa + s);
       cplx beta, u0;
@@ -220,10 +220,10 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
         const double u0a = abs2(u0);
         tau = 2.0 / (1.0 + s / u0a);
       }
-      for (int i = j + 1 + lane; i < m; i += 64) v[i] = cdiv(cj[i], u0);
+      for (int i = j + 1 + lane; i < m; i += 64) v[i] = cdiv(ldg(cj + i), u0);
       if (lane == 0) {
         v[j] = mk(1, 0);
-        cj[j] = beta;
+        stg(cj + j, beta);
         s_tau = tau;
         pos[p] = pos[j];
         pos[j] = cp;
@@ -242,32 +242,32 @@ __device__ void cpqr_one(const IdDesc& D, double tol, int want_T, double* lds) {
     __syncthreads();
   }
   const int k = j;
-  for (int c = tid; c < n; c += NT) D.perm[c] = pos[c];
-  if (tid == 0) *D.rank = k;
+  for (int c = tid; c < n; c += NT) stg(D.perm + c, pos[c]);
+  if (tid == 0) stg(D.rank, k);
   if (want_T) {
     // T = R11^{-1} R12 in place, one column per thread; the row sums are
     // unrolled so that their independent loads are in flight together
     for (int t = k + tid; t < n; t += NT) {
       cplx* col = D.A + ld * pos[t];
       for (int i = k - 1; i >= 0; --i) {
-        cplx s = col[i], s2 = mk(0, 0);
+        cplx s = ldg(col + i), s2 = mk(0, 0);
         int l = i + 1;
 #pragma unroll 4
         for (; l + 1 < k; l += 2) {
-          const cplx r = D.A[i + ld * pos[l]], r2 = D.A[i + ld * pos[l + 1]];
-          const cplx x = col[l], x2 = col[l + 1];
+          const cplx r = ldg(D.A + i + ld * pos[l]), r2 = ldg(D.A + i + ld * pos[l + 1]);
+          const cplx x = ldg(col + l), x2 = ldg(col + l + 1);
           s.re -= r.re * x.re - r.im * x.im;
           s.im -= r.re * x.im + r.im * x.re;
           s2.re -= r2.re * x2.re - r2.im * x2.im;
           s2.im -= r2.re * x2.im + r2.im * x2.re;
         }
         if (l < k) {
-          const cplx r = D.A[i + ld * pos[l]];
-          const cplx x = col[l];
+          const cplx r = ldg(D.A + i + ld * pos[l]);
+          const cplx x = ldg(col + l);
           s.re -= r.re * x.re - r.im * x.im;
           s.im -= r.re * x.im + r.im * x.re;
         }
-        col[i] = cdiv(s + s2, D.A[i + ld * pos[i]]);
+        stg(col + i, cdiv(s + s2, ldg(D.A + i + ld * pos[i])));
       }
     }
   }

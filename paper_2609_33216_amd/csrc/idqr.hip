@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_id_qr(const IdDesc* __restrict__ descs)
       for (int r = 0; r < RPL; ++r) {
         const int row = lane + 64 * r;
         a[q][r] = mk(0, 0);
-        if (jq < nb && row < m) a[q][r] = A[row + ld * (j0 + jq)];
+        if (jq < nb && row < m) a[q][r] = ldg(A + row + ld * (j0 + jq));
       }
     }
     for (int w4 = 0; w4 < 4; ++w4)
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_id_qr(const IdDesc* __restrict__ descs)
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           const int row = lane + 64 * r;
-          if (row >= j0 && row < m) A[row + ld * (j0 + jq)] = a[q][r];
+          if (row >= j0 && row < m) stg(A + row + ld * (j0 + jq), a[q][r]);
         }
       }
     }
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_id_qr(const IdDesc* __restrict__ descs)
     auto vop = [&](int rr, int i) -> cplx {
       if (i >= nsteps || rr < i || j0 + rr >= m) return mk(0, 0);
       if (rr == i) return mk(1, 0);
-      return A[(j0 + rr) + ld * (j0 + i)];
+      return ldg(A + (j0 + rr) + ld * (j0 + i));
     };
     const int K = m - j0;
     const int c_first = j0 + kQrNb;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_id_qr(const IdDesc* __restrict__ descs)
         const int rr = 4 * lk + s;
         vv[s] = vop(rr, lq);
         at[s] = mk(0, 0);
-        if (colok && j0 + rr < m) at[s] = A[(j0 + rr) + ld * (c0 + lq)];
+        if (colok && j0 + rr < m) at[s] = ldg(A + (j0 + rr) + ld * (c0 + lq));
       }
       for (int g = 0; g < K; g += 16) {
         // the next group's operands are loaded while this one is multiplied
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_id_qr(const IdDesc* __restrict__ descs)
           const int rr = g + 16 + 4 * lk + s;
           vn[s] = vop(rr, lq);
           an[s] = mk(0, 0);
-          if (colok && j0 + rr < m) an[s] = A[(j0 + rr) + ld * (c0 + lq)];
+          if (colok && j0 + rr < m) an[s] = ldg(A + (j0 + rr) + ld * (c0 + lq));
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_id_qr(const IdDesc* __restrict__ descs)
         const int col = c0 + 4 * s + lk;
         vu[s] = vop(lq, 4 * s + lk);
         cu[s] = mk(0, 0);
-        if (j0 + lq < m && col < n) cu[s] = A[(j0 + lq) + ld * col];
+        if (j0 + lq < m && col < n) cu[s] = ldg(A + (j0 + lq) + ld * col);
       }
       for (int g = 0; g < K; g += 16) {
         cplx vn[4], cn[4];
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_id_qr(const IdDesc* __restrict__ descs)
           const int rown = j0 + g + 16 + lq, col = c0 + 4 * s + lk;
           vn[s] = vop(g + 16 + lq, 4 * s + lk);
           cn[s] = mk(0, 0);
-          if (rown < m && col < n) cn[s] = A[rown + ld * col];
+          if (rown < m && col < n) cn[s] = ldg(A + rown + ld * col);
         }
         qr_d4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
 #pragma unroll
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_id_qr(const IdDesc* __restrict__ descs)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int col = c0 + 4 * r + lk;
-            if (col < n) A[row + ld * col] = mk(cu[r].re - dr[r], cu[r].im - di[r]);
+            if (col < n) stg(A + row + ld * col, mk(cu[r].re - dr[r], cu[r].im - di[r]));
           }
         }
 #pragma unroll
@@ -359,9 +359,9 @@ __global__ __launch_bounds__(kSqThreads) void k_id_sq(const IdDesc* __restrict__
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = t & 7, c = t >> 3;
   constexpr int nw = kSqWaves;
 
-  const int j0 = (D.target >= 0) ? *D.rank : 0;
+  const int j0 = (D.target >= 0) ? ldg(D.rank) : 0;
   if (j0 > 0)
-    for (int q = t; q < n; q += kSqThreads) posl[D.perm[q]] = q;  // inverse of perm, used once
+    for (int q = t; q < n; q += kSqThreads) posl[ldg(D.perm + q)] = q;  // inverse of perm, used once
   __syncthreads();
   const bool ok = c < n;
   int pos = ok ? (j0 > 0 ? posl[c] : c) : (1 << 20);
@@ -374,12 +374,12 @@ __global__ __launch_bounds__(kSqThreads) void k_id_sq(const IdDesc* __restrict__
     for (int e = 0; e < 16; ++e) {
       const int row = 16 * g + e;
       a[e] = mk(0, 0);
-      if (ok && row < m && (j0 > 0 || row <= c)) a[e] = D.A[row + ld * c];
+      if (ok && row < m && (j0 > 0 || row <= c)) a[e] = ldg(D.A + row + ld * c);
       if (row >= j0) s += abs2(a[e]);
     }
     vn = group8_sum(s);
   }
-  double r00 = (j0 > 0) ? *D.r00 : 0.0;
+  double r00 = (j0 > 0) ? ldg(D.r00) : 0.0;
   const int kmax = m < n ? m : n;
   int j = j0;
   for (; j < kmax; ++j) {
@@ -479,17 +479,17 @@ __global__ __launch_bounds__(kSqThreads) void k_id_sq(const IdDesc* __restrict__
   }
   const int k = j;
   if (t == 0) {
-    *D.rank = k;
-    if (j0 == 0) *D.r00 = r00;
+    stg(D.rank, k);
+    if (j0 == 0) stg(D.r00, r00);
   }
-  if (ok && g == 0) D.perm[pos] = c;
+  if (ok && g == 0) stg(D.perm + pos, c);
   if (!want_T) {
     // the state, for a pass that resumes
     if (ok) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int row = 16 * g + e;
-        if (row < m) D.A[row + ld * c] = a[e];
+        if (row < m) stg(D.A + row + ld * c, a[e]);
       }
     }
     return;
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(kSqThreads) void k_id_sq(const IdDesc* __restrict__
   __syncthreads();
   for (int e = t; e < nt * k; e += kSqThreads) {
     const int q = e / k, i = e % k;
-    D.A[i + ld * posl[k + q]] = Bt[e];
+    stg(D.A + i + ld * posl[k + q], Bt[e]);
   }
 }
 
