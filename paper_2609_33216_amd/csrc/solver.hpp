@@ -341,9 +341,9 @@ class Solver {
   void run_gemm(const std::vector<typename S::GemmDesc>& g, int count, int mmax, int nmax);
   void run_cpqr(const IdDesc* d, int count, int mmax, int nmax, int want_T, cplx* data, size_t data_elems, int* ints,
                 size_t nints, double* dbl, size_t ndbl);
-  // returns 1 if the multi-workgroup LU ran (net permutation in the pivots),
-  // 0 for k_lu_fused (row interchanges); multi_ok: the descriptors carry the
-  // multi-workgroup LU's workspace
+  // returns 1 if the pivots hold the net permutation (the multi-workgroup LU,
+  // or k_lu_fused up to order kLuPermLds), 0 for row interchanges; multi_ok:
+  // the descriptors carry the multi-workgroup LU's workspace
   int run_lu(const LuDesc* d, int count, int nmax, int ncolmax, int nrhsmax, cplx* data, size_t data_elems,
              double flops, bool multi_ok);
   void solve_enqueue(const cplx* db, cplx* dx, int nrhs);
