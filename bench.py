@@ -602,6 +602,7 @@ def main():
     ap.add_argument("--proxy-margin", type=int, default=16,
                     help="predictor mode: proxy points added to the predicted rank")
     ap.add_argument("--autotune", action="store_true", help="single-boundary mode: autotuned launch variants")
+    ap.add_argument("--graphs", action="store_true", help="single-boundary mode: solves replayed as HIP graphs")
     ap.add_argument("--n4", type=int, default=None, help="mixed mode: another N for the seven-arm star")
     ap.add_argument("--kite-max", type=int, default=None, help="kite sweep: largest DOF")
     ap.add_argument("--no-bm", action="store_true", help="kite sweep: without the Burton-Miller column")
@@ -643,7 +644,7 @@ def main():
     x = torch.zeros(2 * n, dtype=torch.complex128, device=dev)
     torch.cuda.synchronize()  # the solver queues on its own stream
     s = binding.Solver(0)
-    s.configure(pipeline=not args.no_pipeline, autotune=args.autotune)
+    s.configure(pipeline=not args.no_pipeline, autotune=args.autotune, graphs=args.graphs)
 
     rm = args.root_max if args.root_max_given else 0
     t_sym, st, per = _run_form(s, wl, binding.MULLER_SYM, args.steps, args.warmup, b, x, torch, rm)
@@ -675,7 +676,7 @@ def main():
         "config": {"workload": wl.name, "curve": f"{wl.curve} {dict(wl.curve_params)}", "n_nodes": n,
                    "unknowns": 2 * n, "k_out": wl.k0, "k_in": wl.k1, "leaf": wl.leaf, "tol": wl.tol,
                    "form": "symmetric one-sided ID", "pipelined_factor": not args.no_pipeline,
-                   "autotune": args.autotune,
+                   "autotune": args.autotune, "graphs": args.graphs,
                    "parallelism": "1 GPU"},
         "t_compress": round(st["t_compress"], 6),
         "t_compress_host": round(st["t_compress"] - st["t_compress_wait"], 6),
