@@ -370,6 +370,13 @@ class Solver {
              const std::vector<int>& c2);
   };
   void run_kblock(KBatch& kb, int timer_kind);
+  // host staging reused from call to call (their lists keep their storage)
+  struct JobPiece {
+    std::vector<int> rp, r1, r2, cp, c1, c2;
+  };
+  std::vector<JobPiece> pieces_;  // per-box job lists of the proxy matrices
+  KBatch kbw_;                    // the proxy matrices' kernel-block batch
+  std::vector<KTile> tiles_;      // tiles of the current kernel-block batch
   void root_block_jobs(KBatch& kb, const Tree& T, int t, cplx* out, int ld, const std::vector<int>& offs);
   PointsDev tree_points(const Tree& T) const;
   PointsDev points() const;
