@@ -90,15 +90,23 @@ def _workload(cfg: int):
     raise SystemExit(f"unknown config {cfg}")
 
 
-def _run_form(s, wl, form, steps, warmup, b, x, torch, root_max=0):
+def _run_form(s, wl, form, steps, warmup, b, x, torch, root_max=0, fused=True):
     x_, dx_, ddx_ = wl.boundary()
     s.assemble(x_, dx_, ddx_, wl.k0, wl.k1, wl.eps0, wl.eps1, leaf=wl.leaf, tol=wl.tol, form=form,
                n_proxy=wl.n_proxy if wl.n_proxy > 0 else 64, proxy_ratio=wl.proxy_ratio, root_max=root_max)
     s.rhs_plane_wave_device(wl.angle, b.data_ptr())
+    def factor_and_solve():
+        # one call (the solve's sweep up the levels beside the top-level LU),
+        # or the two calls one after the other
+        if fused:
+            s.factor_solve_device(b.data_ptr(), x.data_ptr())
+        else:
+            s.factor()
+            s.solve_device(b.data_ptr(), x.data_ptr())
+
     for _ in range(warmup):
         s.compress()
-        s.factor()
-        s.solve_device(b.data_ptr(), x.data_ptr())
+        factor_and_solve()
     torch.cuda.synchronize()
     per = []
     phases = {"t_compress": [], "t_factor": [], "t_solve": []}
@@ -106,8 +114,7 @@ def _run_form(s, wl, form, steps, warmup, b, x, torch, root_max=0):
     for _ in range(steps):
         ts = time.perf_counter()
         s.compress()
-        s.factor()
-        s.solve_device(b.data_ptr(), x.data_ptr())
+        factor_and_solve()
         torch.cuda.synchronize()
         per.append(time.perf_counter() - ts)
         st = s.stats()
@@ -603,6 +610,8 @@ def main():
                     help="predictor mode: proxy points added to the predicted rank")
     ap.add_argument("--autotune", action="store_true", help="single-boundary mode: autotuned launch variants")
     ap.add_argument("--graphs", action="store_true", help="single-boundary mode: solves replayed as HIP graphs")
+    ap.add_argument("--separate-calls", action="store_true",
+                    help="single-boundary mode: symhss_factor then symhss_solve instead of symhss_factor_solve")
     ap.add_argument("--n4", type=int, default=None, help="mixed mode: another N for the seven-arm star")
     ap.add_argument("--kite-max", type=int, default=None, help="kite sweep: largest DOF")
     ap.add_argument("--no-bm", action="store_true", help="kite sweep: without the Burton-Miller column")
@@ -647,7 +656,8 @@ def main():
     s.configure(pipeline=not args.no_pipeline, autotune=args.autotune, graphs=args.graphs)
 
     rm = args.root_max if args.root_max_given else 0
-    t_sym, st, per = _run_form(s, wl, binding.MULLER_SYM, args.steps, args.warmup, b, x, torch, rm)
+    fused = not args.separate_calls
+    t_sym, st, per = _run_form(s, wl, binding.MULLER_SYM, args.steps, args.warmup, b, x, torch, rm, fused)
     resid = None
     if not args.no_residual:
         y = torch.zeros_like(x)
@@ -677,7 +687,9 @@ def main():
                    "unknowns": 2 * n, "k_out": wl.k0, "k_in": wl.k1, "leaf": wl.leaf, "tol": wl.tol,
                    "form": "symmetric one-sided ID", "pipelined_factor": not args.no_pipeline,
                    "autotune": args.autotune, "graphs": args.graphs,
-                   "parallelism": "1 GPU"},
+                   "factor_solve": not args.separate_calls, "parallelism": "1 GPU"},
+        # with factor_solve, t_factor is the time to queue the top-level LU; its
+        # GPU time, beside the solve's sweep up the levels, falls in t_solve
         "t_compress": round(st["t_compress"], 6),
         "t_compress_host": round(st["t_compress"] - st["t_compress_wait"], 6),
         "host_seconds": {k: round(st["t_host_" + k], 6) for k in ("plan", "ids", "post", "factor")},
@@ -737,7 +749,7 @@ def main():
 
     if not args.no_base:
         # the unscaled two-sided baseline over the same steps and warm-up
-        t_base, stb, _ = _run_form(s, wl, binding.MULLER_BASE, args.steps, args.warmup, b, x, torch, rm)
+        t_base, stb, _ = _run_form(s, wl, binding.MULLER_BASE, args.steps, args.warmup, b, x, torch, rm, fused)
         out["nonsym"] = {"s_per_solve": round(t_base, 6), "t_compress": round(stb["t_compress"], 6),
                          "t_factor": round(stb["t_factor"], 6), "t_solve": round(stb["t_solve"], 6),
                          "t_compress_host": round(stb["t_compress"] - stb["t_compress_wait"], 6),

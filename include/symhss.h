@@ -138,6 +138,15 @@ symhss_status symhss_compress(symhss_ctx *ctx);
  * returns SYMHSS_ESTATE until a factor succeeds). */
 symhss_status symhss_factor(symhss_ctx *ctx);
 
+/* symhss_factor followed by symhss_solve, with the same results and errors
+ * (ESINGULAR on a zero pivot is reported after x was written).  With the
+ * factorisation pipelined during compress (SYMHSS_OPT_PIPELINE, FP64, no
+ * graphs) the solve's sweep up the levels runs while the top-level LU
+ * (Section 4.2, the dense root system) is still being computed, and waits
+ * for it only before its top-level part; otherwise the two calls run one
+ * after the other.  Arguments as for symhss_solve. */
+symhss_status symhss_factor_solve(symhss_ctx *ctx, const symhss_z *b, symhss_z *x, int32_t nrhs, int32_t flags);
+
 /* Solve A x = b for nrhs right-hand sides.  b and x are 2N x nrhs column-
  * major in the block order [q; u] and the scaling of the chosen form (row-
  * scaled for SYMHSS_MULLER_SYM* and SYMHSS_PMCHWT_SYM, unscaled for the

@@ -83,7 +83,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = [
     "symhss_create", "symhss_destroy", "symhss_last_error", "symhss_stream", "symhss_assemble",
-    "symhss_compress", "symhss_factor", "symhss_solve", "symhss_rhs_plane_wave", "symhss_eval_entries",
+    "symhss_compress", "symhss_factor", "symhss_factor_solve", "symhss_solve", "symhss_rhs_plane_wave",
+    "symhss_eval_entries",
     "symhss_eval_bessel", "symhss_matvec_direct", "symhss_get_stats", "symhss_box_query",
     "symhss_assemble_batch", "symhss_rhs_plane_wave_batch", "symhss_configure",
     "symhss_predictor_train", "symhss_predictor_load", "symhss_predictor_get", "symhss_predictor_predict",
@@ -129,6 +130,7 @@ def load(path: str | None = None):
         "symhss_compress": ([vp], ctypes.c_int),
         "symhss_factor": ([vp], ctypes.c_int),
         "symhss_solve": ([vp, vp, vp, i32, i32], ctypes.c_int),
+        "symhss_factor_solve": ([vp, vp, vp, i32, i32], ctypes.c_int),
         "symhss_rhs_plane_wave": ([vp, dbl, vp, i32], ctypes.c_int),
         "symhss_eval_entries": ([vp, i64, vp, i64, vp, vp], ctypes.c_int),
         "symhss_eval_bessel": ([vp, i64, vp, vp], ctypes.c_int),
@@ -330,6 +332,23 @@ class Solver:
         X = np.zeros_like(B, order="F")
         self._check(self.lib.symhss_solve(self.h, _ptr(B), _ptr(X), B.shape[1], 0))
         return X[:, 0].copy() if one else X
+
+    def factor_solve(self, b):
+        """factor() then solve(b) in one call (the solve's sweep up the levels
+        beside the top-level LU); b as for solve."""
+        b = np.asarray(b, dtype=np.complex128)
+        one = b.ndim == 1
+        B = np.asfortranarray(b.reshape(b.shape[0], -1))
+        if B.shape[0] != 2 * self.n:
+            raise ValueError("b must have 2N rows")
+        X = np.zeros_like(B, order="F")
+        self._check(self.lib.symhss_factor_solve(self.h, _ptr(B), _ptr(X), B.shape[1], 0))
+        return X[:, 0].copy() if one else X
+
+    def factor_solve_device(self, b_ptr: int, x_ptr: int, nrhs: int = 1):
+        """factor_solve on HBM addresses of 2N x nrhs complex128."""
+        self._check(self.lib.symhss_factor_solve(self.h, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), nrhs,
+                                                 DEVICE_PTRS))
 
     def solve_device(self, b_ptr: int, x_ptr: int, nrhs: int = 1):
         """Device-resident solve: b_ptr, x_ptr are HBM addresses of 2N x nrhs complex128."""

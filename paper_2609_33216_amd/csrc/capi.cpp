@@ -111,6 +111,10 @@ symhss_status symhss_factor(symhss_ctx* ctx) {
   return guarded(ctx, [&](symhss::Solver& s) { s.factor(); });
 }
 
+symhss_status symhss_factor_solve(symhss_ctx* ctx, const symhss_z* b, symhss_z* x, int32_t nrhs, int32_t flags) {
+  return guarded(ctx, [&](symhss::Solver& s) { s.factor_solve(b, x, nrhs, flags); });
+}
+
 symhss_status symhss_solve(symhss_ctx* ctx, const symhss_z* b, symhss_z* x, int32_t nrhs, int32_t flags) {
   return guarded(ctx, [&](symhss::Solver& s) { s.solve(b, x, nrhs, flags); });
 }

@@ -257,6 +257,9 @@ class Solver {
   void compress();
   void factor();
   void solve(const symhss_z* b, symhss_z* x, int nrhs, int flags);
+  // factor, then solve, with the solve's sweep up the levels run beside the
+  // top-level LU (pipelined FP64 factorisations; otherwise factor + solve)
+  void factor_solve(const symhss_z* b, symhss_z* x, int nrhs, int flags);
   void solve_incident(const symhss_z* uin, const symhss_z* qin, symhss_z* q, symhss_z* u, int nrhs, int flags);
   void plane_wave_incident(const double* angles, symhss_z* uin, symhss_z* qin, int flags);
   void rhs_plane_wave(double angle, symhss_z* b, int flags);
@@ -471,6 +474,13 @@ class Solver {
   hipStream_t fst_ = nullptr;
   hipEvent_t cev_ = nullptr;
   hipEvent_t fev_ = nullptr;   // end of the compression of height pending_factor_
+  // factor_solve: the levels' factorisations done (lev_) and the top-level
+  // LU done (rev_), both on the factor stream; root_wait_ = rev_ while a
+  // solve must wait for the top level before its top-level part
+  hipEvent_t lev_ = nullptr, rev_ = nullptr;
+  hipEvent_t root_wait_ = nullptr;
+  void solve_impl(const symhss_z* b, symhss_z* x, int nrhs, int flags);
+  void factor_finish();  // pivot checks and device-byte statistics
   int pending_factor_ = -1;    // compressed height whose pipelined factorisation is not queued yet
   Uploader fup2_;
   int pipeline_opt_ = 1;
