@@ -337,6 +337,8 @@ class Solver {
   void queue_pending_factor();
   void factor_level(int h);
   void factor_root();
+  void factor_root_blocks();
+  void factor_root_lu();
   void factor_enqueue();
   uint64_t plan_signature() const;
   // launches with a choice of variant (autotuned per size bucket when enabled)
