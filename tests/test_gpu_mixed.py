@@ -108,3 +108,29 @@ def test_mixed_batch():
         _, _, A, bo = oracle_system(w)
         assert rel(x[o:o + 2 * w.n], dense.solve_dense(A, bo)) < 1e-8
         o += 2 * w.n
+
+
+def test_refinement_converges_with_a_large_top_level_system():
+    """The seven-arm star at N = 262144, k = 200/300 with top-level threshold
+    8192 (a dense top-level system of order about 6200, solved in FP32
+    through inverted 64 x 64 diagonal blocks in every sweep): the refinement
+    must reach its 1e-10 target well within its iteration limit and agree with
+    the FP64 path's solution.  A less accurate FP32 form of the block
+    inverses once stalled it at the limit."""
+    wl = workloads.config4()
+    s = make_solver(wl, root_max=8192)
+    b = s.rhs_plane_wave(wl.angle)
+    s.compress()
+    s.factor()
+    x64 = s.solve(b)
+    s.configure(mixed=True)
+    s.compress()
+    s.factor()
+    x = s.solve(b)
+    st = s.stats()
+    print("N", wl.n, "top-level order", st["root_size"], "iters", st["refine_iters"], "fp32 residual",
+          st["fp32_residual"], "refined", st["refine_residual"], "vs fp64", rel(x, x64))
+    assert st["root_size"] > 4096
+    assert st["refine_residual"] <= 1e-10
+    assert st["refine_iters"] <= 8
+    assert rel(x, x64) < 1e-8
