@@ -84,12 +84,22 @@ struct ConvDesc {
   int rows, cols, lds, ldd;
 };
 void launch_convert_batched(hipStream_t st, const ConvDesc* d, int count, long maxelems);
+// FP32 blocks placed in an FP64 matrix: dst[rmap[i] + ldd cmap[j]] = src[i + lds j]
+struct Scatter2WideDesc {
+  const cplxf* src;
+  cplx* dst;
+  const int* rmap;
+  const int* cmap;
+  int m, n, lds, ldd;
+};
+void launch_scatter2_widen(hipStream_t st, const Scatter2WideDesc* d, int count, long maxelems);
 // descriptor upload from pinned staging memory by a copy kernel (upload.hip)
 void launch_upload(hipStream_t st, void* dst, const void* src_pinned, size_t bytes);
 // na arrays of n doubles, back to back in pinned staging: array a to dst + a ld
 void launch_upload_split(hipStream_t st, double* dst, size_t ld, const double* src_pinned, size_t n, int na);
 void launch_round_vec(hipStream_t st, const cplx* x, cplxf* y, long n);
 void launch_add_vec(hipStream_t st, cplx* x, const cplxf* d, long n);
+void launch_widen_vec(hipStream_t st, const cplxf* x, cplx* y, long n);
 void launch_sub_vec(hipStream_t st, const cplx* b, const cplx* y, cplx* r, long n);
 void launch_col_norm2(hipStream_t st, const cplx* v, long n, long ld, int ncols, double* out);
 

@@ -15,6 +15,24 @@ __global__ void k_convert_batched(const ConvDesc* __restrict__ descs) {
   }
 }
 
+// FP32 blocks placed in an FP64 matrix (the dense top-level system's diagonal
+// blocks, factored in FP64)
+__global__ void k_scatter2_widen(const Scatter2WideDesc* __restrict__ descs) {
+  const Scatter2WideDesc S = descs[blockIdx.y];
+  const int total = S.m * S.n;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int i = e % S.m, j = e / S.m;
+    const cplxf v = S.src[i + (long)S.lds * j];
+    S.dst[S.rmap[i] + (long)S.ldd * S.cmap[j]] = cplx{(double)v.re, (double)v.im};
+  }
+}
+
+// y = (double) x
+__global__ void k_widen_vec(const cplxf* __restrict__ x, cplx* __restrict__ y, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    y[e] = cplx{(double)x[e].re, (double)x[e].im};
+}
+
 // y = (float) x
 __global__ void k_round_vec(const cplx* __restrict__ x, cplxf* __restrict__ y, long n) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
@@ -57,6 +75,19 @@ void launch_convert_batched(hipStream_t st, const ConvDesc* d, int count, long m
   if (count <= 0 || maxelems <= 0) return;
   hipLaunchKernelGGL(k_convert_batched, dim3(grid_for(maxelems) < 1024 ? grid_for(maxelems) : 1024, count),
                      dim3(256), 0, st, d);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_scatter2_widen(hipStream_t st, const Scatter2WideDesc* d, int count, long maxelems) {
+  if (count <= 0 || maxelems <= 0) return;
+  hipLaunchKernelGGL(k_scatter2_widen, dim3(grid_for(maxelems) < 1024 ? grid_for(maxelems) : 1024, count),
+                     dim3(256), 0, st, d);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_widen_vec(hipStream_t st, const cplxf* x, cplx* y, long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_widen_vec, dim3(grid_for(n)), dim3(256), 0, st, x, y, n);
   HIPCHK(hipGetLastError());
 }
 

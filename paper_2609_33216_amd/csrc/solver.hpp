@@ -359,6 +359,7 @@ class Solver {
   struct Sweep32;
   template <class S>
   void solve_sweep(const typename S::C* db, typename S::C* dx, int nrhs);
+  void root_solve_widened(int nrhs);
   // mixed precision: FP32 factorisation, FP64 HSS product, refinement
   void factor_level_mixed(int h);
   void factor_root_mixed();
@@ -433,6 +434,9 @@ class Solver {
   DBuf<cplx> rootF_, rootG_;
   // mixed precision
   int precision_ = 0;               // 0 FP64, 1 FP32 factorisation + FP64 refinement
+  // mixed precision: the dense top-level system stays FP64 (its LU and block
+  // inverses; the sweeps widen their vector for it and round the result)
+  static constexpr bool kMixedRoot64 = true;
   int refine_digits_ = 10, refine_maxit_ = 10;
   DBuf<cplx> root_gen_;             // off-diagonal blocks of the top-level systems (FP64)
   DBuf<f32::cplx> rootf_, rootFf_, rootGf_;

@@ -112,11 +112,12 @@ def test_mixed_batch():
 
 def test_refinement_converges_with_a_large_top_level_system():
     """The seven-arm star at N = 262144, k = 200/300 with top-level threshold
-    8192 (a dense top-level system of order about 6200, solved in FP32
-    through inverted 64 x 64 diagonal blocks in every sweep): the refinement
-    must reach its 1e-10 target well within its iteration limit and agree with
-    the FP64 path's solution.  A less accurate FP32 form of the block
-    inverses once stalled it at the limit."""
+    8192 (a dense top-level system of order about 6200, kept in FP64 by the
+    mixed path and solved through inverted 64 x 64 diagonal blocks in every
+    sweep): the refinement must reach its 1e-10 target well within its
+    iteration limit and agree with the FP64 path's solution.  A less accurate
+    form of the block inverses once stalled it at the limit, when the
+    top-level system was FP32."""
     wl = workloads.config4()
     s = make_solver(wl, root_max=8192)
     b = s.rhs_plane_wave(wl.angle)
@@ -132,5 +133,5 @@ def test_refinement_converges_with_a_large_top_level_system():
           st["fp32_residual"], "refined", st["refine_residual"], "vs fp64", rel(x, x64))
     assert st["root_size"] > 4096
     assert st["refine_residual"] <= 1e-10
-    assert st["refine_iters"] <= 8
-    assert rel(x, x64) < 1e-8
+    assert st["refine_iters"] <= 5
+    assert rel(x, x64) < 1e-9
