@@ -101,7 +101,9 @@ void launch_round_vec(hipStream_t st, const cplx* x, cplxf* y, long n);
 void launch_add_vec(hipStream_t st, cplx* x, const cplxf* d, long n);
 void launch_widen_vec(hipStream_t st, const cplxf* x, cplx* y, long n);
 void launch_sub_vec(hipStream_t st, const cplx* b, const cplx* y, cplx* r, long n);
-void launch_col_norm2(hipStream_t st, const cplx* v, long n, long ld, int ncols, double* out);
+// squared 2-norms of ncols columns; work holds kNormParts doubles per column
+constexpr int kNormParts = 64;
+void launch_col_norm2(hipStream_t st, const cplx* v, long n, long ld, int ncols, double* out, double* work);
 
 // the same in complex FP32 (dense32.hip)
 namespace f32 {

@@ -53,20 +53,36 @@ __global__ void k_sub_vec(const cplx* __restrict__ b, const cplx* __restrict__ y
     r[e] = b[e] - y[e];
 }
 
-// out[c] = sum_i |v[i + ld c]|^2, one workgroup per column, fixed summation order
-__global__ __launch_bounds__(1024) void k_col_norm2(const cplx* __restrict__ v, long n, long ld,
-                                                    double* __restrict__ out) {
-  __shared__ double part[1024];
-  const cplx* col = v + ld * blockIdx.x;
+// out[c] = sum_i |v[i + ld c]|^2 in two stages with a fixed summation order:
+// kNormParts workgroups per column each sum a contiguous part into
+// part[c kNormParts + p], then one workgroup per column adds the parts.
+__global__ __launch_bounds__(256) void k_col_norm2_parts(const cplx* __restrict__ v, long n, long ld,
+                                                         double* __restrict__ part) {
+  __shared__ double red[256];
+  const cplx* col = v + ld * blockIdx.y;
+  const long chunk = (n + kNormParts - 1) / kNormParts;
+  const long i0 = chunk * blockIdx.x, i1 = i0 + chunk < n ? i0 + chunk : n;
   double s = 0.0;
-  for (long i = threadIdx.x; i < n; i += blockDim.x) s += abs2(col[i]);
-  part[threadIdx.x] = s;
+  for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) s += abs2(col[i]);
+  red[threadIdx.x] = s;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+  if (threadIdx.x == 0) part[(long)kNormParts * blockIdx.y + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kNormParts) void k_col_norm2_sum(const double* __restrict__ part,
+                                                              double* __restrict__ out) {
+  __shared__ double red[kNormParts];
+  red[threadIdx.x] = part[(long)kNormParts * blockIdx.x + threadIdx.x];
+  __syncthreads();
+  for (int w = kNormParts / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 static int grid_for(long n) { return (int)std::min<long>(std::max<long>(cdiv_int(n, 256), 1), 8192); }
@@ -109,9 +125,10 @@ void launch_sub_vec(hipStream_t st, const cplx* b, const cplx* y, cplx* r, long 
   HIPCHK(hipGetLastError());
 }
 
-void launch_col_norm2(hipStream_t st, const cplx* v, long n, long ld, int ncols, double* out) {
+void launch_col_norm2(hipStream_t st, const cplx* v, long n, long ld, int ncols, double* out, double* work) {
   if (ncols <= 0) return;
-  hipLaunchKernelGGL(k_col_norm2, dim3(ncols), dim3(1024), 0, st, v, n, ld, out);
+  hipLaunchKernelGGL(k_col_norm2_parts, dim3(kNormParts, ncols), dim3(256), 0, st, v, n, ld, work);
+  hipLaunchKernelGGL(k_col_norm2_sum, dim3(ncols), dim3(kNormParts), 0, st, work, out);
   HIPCHK(hipGetLastError());
 }
 
