@@ -55,9 +55,9 @@ MI355X_HBM_TBS = 8.0
 # triangle (k_id_qr + k_id_sq) for many matrices, or k_cpqr for few; its
 # figure is the mean over the five ID launches of a step.
 MEASURED_TRAFFIC = {
-    "id": {"sources": {"idqr.hip": "7e597cd35c9ff6a3", "cpqr.hip": "5a4bcc5299aacbf7"}, "bytes": 7.726e+08,
+    "id": {"sources": {"idqr.hip": "7e597cd35c9ff6a3", "cpqr.hip": "5a4bcc5299aacbf7"}, "bytes": 7.733e+08,
            "profile": "profiles/id_star5-n32768.md"},
-    "k_lu_fused": {"sources": {"dense_body.inc": "d42beff328f39bce"}, "bytes": 7.486e+08,
+    "k_lu_fused": {"sources": {"dense_body.inc": "deeda13ca7b2dbdf"}, "bytes": 7.483e+08,
                    "profile": "profiles/k_lu_fused_star5-n32768.md"},
     "k_kblock": {"sources": {"kblock.hip": "b8965c325ada25df"}, "bytes": 7.427e+07,
                  "profile": "profiles/k_kblock_star5-n32768.md"},
